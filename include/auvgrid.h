@@ -1,0 +1,188 @@
+/*
+ * auvgrid — gridding scattered multibeam soundings on one MI355X (gfx950).
+ *
+ * C ABI of libauvgrid.so.  Plain pointers and sizes only.  Pointers marked
+ * "device" must be device memory of the current HIP device (any allocator);
+ * pointers marked "host" are ordinary host memory.  The caller owns every
+ * buffer; the library owns only the opaque handles it returns and frees them
+ * in the matching *_destroy call.
+ *
+ * Streams: `auv_stream` is a hipStream_t (NULL = the legacy default stream).
+ * Argument validation is synchronous and returns a status; kernels are only
+ * enqueued on the given stream.  A device fault surfaces as AUV_ERR_HIP from a
+ * later call.  No call synchronises the stream unless its comment says so.
+ *
+ * Errors: every call returns an auv_status; on failure auv_last_error()
+ * returns a message for the calling thread.  No exception crosses the ABI.
+ *
+ * Source of the method: "Towards Real-Time Interpolation for Enhanced AUV
+ * Deep Sea Mapping" (Saxena).  The paper defines bilinear interpolation
+ * (Sec. III-A), NaN samples as invalid candidates (Sec. III-B, III-D), holes
+ * where bilinear has no value (Sec. III-D, V-B), a "nearest n valid candidate
+ * neighbours" helper (Sec. III-D) and GPU-resident real-time interpolation
+ * with the host only in control (Sec. IV).  The radius-limited IDW and the
+ * nearest-neighbour gridding below generalise that helper; their exact
+ * definitions are given at each entry point.
+ *
+ * Geometry.  A grid is pixel-centred: node (row a, column b) sits at
+ * (x0 + (b + 1/2) dx, y0 + (a + 1/2) dy) in projected metres (Sec. III, Fig. 1:
+ * the interpolated value sits at the centre of its cell).  Every grid array is
+ * row-major [ny][nx], element a*nx + b.
+ *
+ * Lattice.  Every discrete decision (bin, radius membership, ranking, hit,
+ * nearest pick) is taken exactly on a lattice of 2^-16 m relative to the
+ * grid's lower-left corner: X = rne((x - x0) 2^16) for a sounding,
+ * X_b = rne(((b + 1/2) dx) 2^16) for a node, R = rne(r 2^16) for a radius,
+ * D^2 = dX^2 + dY^2, member iff D^2 <= R^2 (closed disk).  The key (D^2,
+ * original index) ranks candidates.
+ */
+#ifndef AUVGRID_H
+#define AUVGRID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *auv_stream; /* hipStream_t */
+
+typedef enum {
+    AUV_OK = 0,
+    AUV_ERR_INVALID = -1, /* a bad argument (null pointer, bad size, ...)     */
+    AUV_ERR_RANGE = -2,   /* grid/radius/bin too large for the int32 lattice  */
+    AUV_ERR_BUDGET = -3,  /* workspace or arena too small                     */
+    AUV_ERR_HIP = -4,     /* a HIP runtime call failed                        */
+    AUV_ERR_STATE = -5    /* call not valid in the object's current state     */
+} auv_status;
+
+/* Grid descriptor.  Limits: nx, ny >= 1; dx, dy > 0; nx*dx and ny*dy below
+ * 16384 m (the lattice must fit in 31 bits with its halo). */
+typedef struct {
+    double x0, y0; /* lower-left corner of the grid, projected metres */
+    double dx, dy; /* node spacing (metres)                            */
+    int32_t nx, ny;
+} auv_grid_desc;
+
+typedef struct auv_grid auv_grid; /* immutable validated grid */
+typedef struct auv_bins auv_bins; /* soundings binned for one grid and radius */
+
+/* Precision variants of the IDW distance and weight arithmetic. */
+enum {
+    AUV_P_FP32_REBASE = 0,   /* FP64 rebase to the grid lattice, FP32 weights */
+    AUV_P_FP16_OFFSETS = 1,  /* FP16 offsets from the tile centre, FP32 sums  */
+    AUV_P_FP32_ABSOLUTE = 2  /* FP32 absolute coordinates, no rebase          */
+};
+
+typedef struct {
+    double power;    /* p > 0: weight d^-p                                  */
+    double radius;   /* r > 0 metres; must not exceed the bins' radius       */
+    int32_t min_pts; /* fewer selected soundings than this -> NaN (0 or 1 = none) */
+    int32_t max_pts; /* cap k on the selected set, 0 = no cap                */
+    int32_t precision; /* AUV_P_*; only AUV_P_FP32_REBASE meets the exact
+                          lattice contract, the others are measured variants */
+    int32_t reserved;  /* must be 0 */
+} auv_idw_params;
+
+/* Library version string (static storage). */
+const char *auv_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *auv_last_error(void);
+
+/* Validate a grid descriptor and return an immutable handle.
+ * Errors: AUV_ERR_INVALID for null pointers or non-positive sizes/spacings,
+ * AUV_ERR_RANGE when the extent exceeds the lattice limit. */
+auv_status auv_grid_create(const auv_grid_desc *desc, auv_grid **out);
+void auv_grid_destroy(auv_grid *grid);
+
+/* Size in bytes of the device workspace auv_bin_points needs for n soundings,
+ * a search radius (metres) and a bin size of 2^bin_log2 lattice units
+ * (bin_log2 in [12, 26]; 0 picks the default: the largest power of two not
+ * above the radius, clamped to that range). */
+auv_status auv_bin_workspace_size(const auv_grid *grid, int64_t n, double radius,
+                                  int32_t bin_log2, size_t *bytes);
+
+/* Bin soundings for one grid (stable counting sort, "cell hash").
+ *   x, y, z  device, float64, n elements each (projected metres; z is the
+ *            signed elevation, negative down).  Read only during the kernels
+ *            enqueued by this call.
+ *   n        0 <= n < 2^31.
+ *   radius   the largest search radius (metres) that will be used with the
+ *            bins; the bin domain is the grid grown by this radius.
+ *   ws       device workspace of at least auv_bin_workspace_size bytes, 256-B
+ *            aligned; it holds the bins and must outlive the returned handle.
+ * A sounding with a non-finite x, y or z is invalid and dropped (NaN samples
+ * are invalid candidates, Sec. III-B / III-D).  A valid sounding outside the
+ * grid grown by the radius cannot reach any node and is dropped too.  Within a
+ * bin, soundings keep ascending original index, so the result is
+ * deterministic.  Enqueues work on `stream`; returns at once. */
+auv_status auv_bin_points(const auv_grid *grid, const double *x, const double *y,
+                          const double *z, int64_t n, double radius,
+                          int32_t bin_log2, void *ws, size_t ws_bytes,
+                          auv_stream stream, auv_bins **out);
+
+/* Geometry of the bins: bins per axis, halo (bins added on each side),
+ * bin_log2 actually used.  Host call, no device work. */
+auv_status auv_bins_info(const auv_bins *bins, int32_t *nbx, int32_t *nby,
+                         int32_t *halo, int32_t *bin_log2);
+
+/* Copy the bins out for inspection.
+ *   cell_start  device, nbx*nby+1 int32: first binned position of each bin
+ *               (exclusive prefix of the counts), nullable;
+ *   perm        device, capacity n int32: original index of each binned
+ *               position, ordered by (bin id, original index), nullable;
+ *   counts      host, 3 int64: binned, invalid, outside.  Synchronises
+ *               `stream` when non-null. */
+auv_status auv_bins_export(const auv_bins *bins, int32_t *cell_start,
+                           int32_t *perm, int64_t *counts, auv_stream stream);
+void auv_bins_destroy(auv_bins *bins);
+
+/* Radius-limited inverse-distance weighting on every node of `grid`.
+ * For node n: C(n) = valid soundings with D^2 <= R^2; S(n) = the first
+ * min(|C|, max_pts) of C ranked by (D^2, original index);
+ *   - if some member of S has D^2 == 0 (a hit) the value is the mean depth of
+ *     those members;
+ *   - else if |S| < min_pts (or S is empty) the value is NaN (a hole);
+ *   - else z = sum w_i z_i / sum w_i over S with w_i = d_i^-p, d_i the
+ *     distance from the node computed from the sounding's double
+ *     coordinates, clamped to [min, max] of the depths in S.
+ * Distances and weights run in FP32 (with the FP64 rebase), the final
+ * num/den division in FP64.  Tolerance against the FP64 definition: 1e-5
+ * relative per node; S, the NaN mask, counts and the nearest pick are exact.
+ *   z_out      device float [ny][nx];
+ *   cnt_out    device int32 [ny][nx] |S|, nullable;
+ *   nn_idx_out device int32 [ny][nx] first member of S (the nearest sounding,
+ *              -1 if none), nullable;
+ *   nn_z_out   device float [ny][nx] its depth (NaN if none), nullable.
+ * `bins` must come from this grid with a radius >= params->radius.
+ * Errors: AUV_ERR_INVALID for bad params or a radius above the bins'. */
+auv_status auv_interp_idw(const auv_grid *grid, const auv_bins *bins,
+                          const auv_idw_params *params, float *z_out,
+                          int32_t *cnt_out, int32_t *nn_idx_out, float *nn_z_out,
+                          auv_stream stream);
+
+/* Nearest-neighbour gridding: for every node, the valid sounding within the
+ * radius that minimises (D^2, original index) — ties go to the lowest
+ * original index.  idx_out (device int32 [ny][nx]) gets its original index or
+ * -1; z_out (device float [ny][nx], nullable) its depth rounded to float, or
+ * NaN.  radius must not exceed the bins' radius. */
+auv_status auv_interp_nearest(const auv_grid *grid, const auv_bins *bins,
+                              double radius, int32_t *idx_out, float *z_out,
+                              auv_stream stream);
+
+/* Bilinear resample (Sec. III-A) of a source grid onto the nodes of a
+ * destination grid.  Each destination node maps to the source index
+ * coordinate u = (x - x0_src)/dx_src - 1/2 (likewise v), clamped to
+ * [0, n-1]; the value is the bilinear blend of the four surrounding source
+ * nodes, and NaN when any of them is NaN (no fallback: a hole, Sec. III-D).
+ *   src  device float [s.ny][s.nx];  dst  device float [d.ny][d.nx]. */
+auv_status auv_resample_bilinear(const float *src, const auv_grid_desc *s,
+                                 float *dst, const auv_grid_desc *d,
+                                 auv_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AUVGRID_H */

@@ -1,0 +1,289 @@
+"""auvgrid: gridding scattered multibeam soundings on one MI355X (gfx950).
+
+Thin Python binding of ``libauvgrid.so`` (C ABI declared in
+``include/auvgrid.h``).  Every function has the name of the C entry point it
+marshals arguments for; all work runs in the library's HIP kernels.  PyTorch
+only supplies device memory and streams.  There is no fallback: if the shared
+library is missing the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libauvgrid.so")
+
+AUV_OK = 0
+AUV_ERR_INVALID = -1
+AUV_ERR_RANGE = -2
+AUV_ERR_BUDGET = -3
+AUV_ERR_HIP = -4
+AUV_ERR_STATE = -5
+
+AUV_P_FP32_REBASE = 0
+AUV_P_FP16_OFFSETS = 1
+AUV_P_FP32_ABSOLUTE = 2
+
+
+class AuvError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"auvgrid status {status}: {msg}")
+        self.status = status
+
+
+class auv_grid_desc(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32)]
+
+
+class auv_idw_params(ctypes.Structure):
+    _fields_ = [("power", ctypes.c_double), ("radius", ctypes.c_double),
+                ("min_pts", ctypes.c_int32), ("max_pts", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libauvgrid.so and declare every exported signature."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"libauvgrid.so not found at {path}: build it with "
+            "`python -m paper_2505_22675_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "auv_version": ([], ctypes.c_char_p),
+        "auv_last_error": ([], ctypes.c_char_p),
+        "auv_grid_create": ([P(auv_grid_desc), P(vp)], ctypes.c_int),
+        "auv_grid_destroy": ([vp], None),
+        "auv_bin_workspace_size": ([vp, i64, d, i32, P(ctypes.c_size_t)], ctypes.c_int),
+        "auv_bin_points": ([vp, vp, vp, vp, i64, d, i32, vp, ctypes.c_size_t, vp, P(vp)],
+                           ctypes.c_int),
+        "auv_bins_info": ([vp, P(i32), P(i32), P(i32), P(i32)], ctypes.c_int),
+        "auv_bins_export": ([vp, vp, vp, P(i64), vp], ctypes.c_int),
+        "auv_bins_destroy": ([vp], None),
+        "auv_interp_idw": ([vp, vp, P(auv_idw_params), vp, vp, vp, vp, vp], ctypes.c_int),
+        "auv_interp_nearest": ([vp, vp, d, vp, vp, vp], ctypes.c_int),
+        "auv_resample_bilinear": ([vp, P(auv_grid_desc), vp, P(auv_grid_desc), vp],
+                                  ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != AUV_OK:
+        raise AuvError(rc, _lib.auv_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _dev(t, dtype, name, numel=None):
+    """Device pointer of a contiguous tensor of the given dtype (or None)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} needs at least {numel} elements, has {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def auv_version() -> str:
+    return load_library().auv_version().decode()
+
+
+def auv_last_error() -> str:
+    return load_library().auv_last_error().decode()
+
+
+class Grid:
+    """Owning wrapper of an ``auv_grid*``."""
+
+    def __init__(self, desc: auv_grid_desc, handle: ctypes.c_void_p):
+        self.desc = desc
+        self._h = handle
+
+    @property
+    def nx(self):
+        return self.desc.nx
+
+    @property
+    def ny(self):
+        return self.desc.ny
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.auv_grid_destroy(self._h)
+            self._h = None
+
+
+def make_desc(x0, y0, dx, dy, nx, ny) -> auv_grid_desc:
+    return auv_grid_desc(float(x0), float(y0), float(dx), float(dy), int(nx), int(ny))
+
+
+def auv_grid_create(desc) -> Grid:
+    """desc: auv_grid_desc or any object with x0, y0, dx, dy, nx, ny."""
+    lib = load_library()
+    if not isinstance(desc, auv_grid_desc):
+        desc = make_desc(desc.x0, desc.y0, desc.dx, desc.dy, desc.nx, desc.ny)
+    h = ctypes.c_void_p()
+    _check(lib.auv_grid_create(ctypes.byref(desc), ctypes.byref(h)))
+    return Grid(desc, h)
+
+
+def auv_grid_destroy(grid: Grid):
+    if grid._h:
+        load_library().auv_grid_destroy(grid._h)
+        grid._h = None
+
+
+def auv_bin_workspace_size(grid: Grid, n: int, radius: float, bin_log2: int = 0) -> int:
+    lib = load_library()
+    out = ctypes.c_size_t()
+    _check(lib.auv_bin_workspace_size(grid.handle, int(n), float(radius), int(bin_log2),
+                                      ctypes.byref(out)))
+    return out.value
+
+
+@dataclass
+class Bins:
+    """Owning wrapper of an ``auv_bins*``; keeps its workspace and inputs alive."""
+    handle: ctypes.c_void_p
+    grid: Grid
+    ws: torch.Tensor
+    n: int
+    radius: float
+    keep: tuple = ()
+
+    def __del__(self):
+        if self.handle and _lib is not None:
+            _lib.auv_bins_destroy(self.handle)
+            self.handle = None
+
+
+def auv_bin_points(grid: Grid, x: torch.Tensor, y: torch.Tensor, z: torch.Tensor,
+                   radius: float, bin_log2: int = 0, ws: torch.Tensor | None = None,
+                   stream=None) -> Bins:
+    """Bin float64 device soundings; allocates the workspace when ws is None."""
+    lib = load_library()
+    n = int(x.numel())
+    px = _dev(x, torch.float64, "x")
+    py = _dev(y, torch.float64, "y", n)
+    pz = _dev(z, torch.float64, "z", n)
+    need = auv_bin_workspace_size(grid, n, radius, bin_log2)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=x.device)
+    pw = _dev(ws, torch.uint8, "ws", need)
+    h = ctypes.c_void_p()
+    _check(lib.auv_bin_points(grid.handle, px, py, pz, n, float(radius), int(bin_log2),
+                              pw, ws.numel(), _stream(stream), ctypes.byref(h)))
+    return Bins(h, grid, ws, n, float(radius), keep=(x, y, z))
+
+
+def auv_bins_info(bins: Bins):
+    """Returns (nbx, nby, halo, bin_log2)."""
+    lib = load_library()
+    v = [ctypes.c_int32() for _ in range(4)]
+    _check(lib.auv_bins_info(bins.handle, *[ctypes.byref(t) for t in v]))
+    return tuple(t.value for t in v)
+
+
+def auv_bins_export(bins: Bins, stream=None):
+    """Returns (cell_start, perm, (n_binned, n_invalid, n_outside)) as device
+    tensors; synchronises the stream."""
+    lib = load_library()
+    nbx, nby, _, _ = auv_bins_info(bins)
+    dev = bins.ws.device
+    cs = torch.empty(nbx * nby + 1, dtype=torch.int32, device=dev)
+    perm = torch.empty(max(bins.n, 1), dtype=torch.int32, device=dev)
+    counts = (ctypes.c_int64 * 3)()
+    _check(lib.auv_bins_export(bins.handle, _dev(cs, torch.int32, "cell_start"),
+                               _dev(perm, torch.int32, "perm"), counts, _stream(stream)))
+    nb = counts[0]
+    return cs, perm[:nb], (counts[0], counts[1], counts[2])
+
+
+def idw_params(power=2.0, radius=6.0, min_pts=1, max_pts=0, precision=AUV_P_FP32_REBASE):
+    return auv_idw_params(float(power), float(radius), int(min_pts), int(max_pts),
+                          int(precision), 0)
+
+
+def auv_interp_idw(grid: Grid, bins: Bins, params: auv_idw_params, z_out: torch.Tensor,
+                   cnt_out=None, nn_idx_out=None, nn_z_out=None, stream=None):
+    lib = load_library()
+    m = grid.nx * grid.ny
+    _check(lib.auv_interp_idw(grid.handle, bins.handle, ctypes.byref(params),
+                              _dev(z_out, torch.float32, "z_out", m),
+                              _dev(cnt_out, torch.int32, "cnt_out", m),
+                              _dev(nn_idx_out, torch.int32, "nn_idx_out", m),
+                              _dev(nn_z_out, torch.float32, "nn_z_out", m),
+                              _stream(stream)))
+
+
+def auv_interp_nearest(grid: Grid, bins: Bins, radius: float, idx_out: torch.Tensor,
+                       z_out=None, stream=None):
+    lib = load_library()
+    m = grid.nx * grid.ny
+    _check(lib.auv_interp_nearest(grid.handle, bins.handle, float(radius),
+                                  _dev(idx_out, torch.int32, "idx_out", m),
+                                  _dev(z_out, torch.float32, "z_out", m),
+                                  _stream(stream)))
+
+
+def auv_resample_bilinear(src: torch.Tensor, s_desc, dst: torch.Tensor, d_desc, stream=None):
+    lib = load_library()
+    if not isinstance(s_desc, auv_grid_desc):
+        s_desc = make_desc(s_desc.x0, s_desc.y0, s_desc.dx, s_desc.dy, s_desc.nx, s_desc.ny)
+    if not isinstance(d_desc, auv_grid_desc):
+        d_desc = make_desc(d_desc.x0, d_desc.y0, d_desc.dx, d_desc.dy, d_desc.nx, d_desc.ny)
+    _check(lib.auv_resample_bilinear(
+        _dev(src, torch.float32, "src", s_desc.nx * s_desc.ny), ctypes.byref(s_desc),
+        _dev(dst, torch.float32, "dst", d_desc.nx * d_desc.ny), ctypes.byref(d_desc),
+        _stream(stream)))
+
+
+# ------------------------------------------------------------ conveniences --
+
+def grid_idw(grid: Grid, bins: Bins, power=2.0, radius=None, min_pts=1, max_pts=0,
+             with_counts=False, with_nearest=False, stream=None):
+    """Allocate outputs and run auv_interp_idw; returns a dict of tensors."""
+    dev = bins.ws.device
+    shape = (grid.ny, grid.nx)
+    out = {"z": torch.empty(shape, dtype=torch.float32, device=dev)}
+    if with_counts:
+        out["cnt"] = torch.empty(shape, dtype=torch.int32, device=dev)
+    if with_nearest:
+        out["nn_idx"] = torch.empty(shape, dtype=torch.int32, device=dev)
+        out["nn_z"] = torch.empty(shape, dtype=torch.float32, device=dev)
+    p = idw_params(power, bins.radius if radius is None else radius, min_pts, max_pts)
+    auv_interp_idw(grid, bins, p, out["z"], out.get("cnt"), out.get("nn_idx"),
+                   out.get("nn_z"), stream)
+    return out

@@ -1,0 +1,121 @@
+// Internal declarations shared by the HIP translation units of libauvgrid.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "auvgrid.h"
+
+namespace auv {
+
+// Lattice: 2^16 units per metre, relative to the grid's lower-left corner.
+constexpr double kLatticePerMetre = 65536.0;
+constexpr int kLatticeLog2 = 16;
+// Residual (sounding position minus its lattice point) is stored as a signed
+// 16-bit fixed-point number of 2^-15 lattice units.
+constexpr float kResidualUnit = 1.0f / 32768.0f;
+
+// Thread-local error message behind auv_last_error().
+auv_status fail(auv_status st, const std::string &msg);
+auv_status hip_fail(hipError_t e, const char *what);
+
+#define AUV_HIP(call)                                                          \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess)                                                  \
+            return ::auv::hip_fail(e_, #call);                                 \
+    } while (0)
+
+}  // namespace auv
+
+// Validated grid plus the lattice coordinates of its extreme nodes.
+struct auv_grid {
+    auv_grid_desc d;
+    int32_t x_last;  // lattice X of node column nx-1
+    int32_t y_last;  // lattice Y of node row ny-1
+};
+
+// Device view of binned soundings.  Binned position k (0 <= k < n_binned)
+// holds the k-th sounding in (bin id, original index) order.
+struct auv_bin_view {
+    const int32_t *cell_start;  // [nbx*nby + 1]
+    const int32_t *X;           // lattice x
+    const int32_t *Y;           // lattice y
+    const uint32_t *res;        // packed residuals: low 16 bits x, high 16 bits y
+    const float *z;             // depth rounded to float
+    const int32_t *idx;         // original index (perm)
+    int32_t nbx, nby, halo, bin_log2;
+    int32_t R;                  // lattice radius the bins were built for
+};
+
+struct auv_bins {
+    auv_bin_view v;
+    const auv_grid *grid;
+    double radius;
+    int64_t n;                  // soundings given
+    int64_t *stats;             // device [4]: binned, invalid, outside, big bins
+    void *ws;
+    size_t ws_bytes;
+};
+
+namespace auv {
+
+// Bin geometry shared by the workspace query and the binning itself.
+struct BinGeom {
+    int32_t R;      // lattice radius
+    int32_t s;      // bin_log2
+    int32_t halo;   // bins added on each side
+    int32_t nbx, nby;
+};
+auv_status bin_geometry(const auv_grid *g, double radius, int32_t bin_log2,
+                        BinGeom *out);
+int32_t default_bin_log2(int32_t R);
+
+// Workspace carve-up of auv_bin_points.
+struct BinWorkspace {
+    int32_t *counts;      // [nb]
+    int32_t *cell_start;  // [nb + 1]
+    int32_t *partials;    // scan partials
+    int32_t *key;         // [n] bin id per input sounding (or -1)
+    int32_t *slot;        // [n] arrival order inside the bin (atomics)
+    int4 *rec;            // [n] rebased record in input order: X, Y, res, z
+    int32_t *perm_tmp;    // [n] unordered perm after the scatter
+    int32_t *X, *Y;       // [n] binned SoA
+    uint32_t *res;
+    float *z;
+    int32_t *idx;
+    int64_t *stats;       // [4]
+    int32_t *big_list;    // [nb] bins too long for one thread
+    size_t bytes;
+};
+size_t bin_workspace_layout(int64_t n, const BinGeom &g, char *base,
+                            BinWorkspace *w);
+
+auv_status launch_binning(const auv_grid *g, const BinGeom &geom,
+                          const double *x, const double *y, const double *z,
+                          int64_t n, const BinWorkspace &w, hipStream_t st);
+
+// IDW / nearest kernels.
+struct IdwArgs {
+    double x_first, y_first;  // unused placeholder for alignment
+    double dx, dy;            // grid spacing (metres)
+    int32_t nx, ny;
+    int32_t R;                // lattice search radius
+    float power;
+    int32_t min_pts, max_pts;
+    int32_t precision;
+    int32_t mode;             // bit 0: IDW value, bit 1: nearest outputs
+    float *z_out;
+    int32_t *cnt_out;
+    int32_t *nn_idx_out;
+    float *nn_z_out;
+};
+auv_status launch_idw(const auv_bin_view &bins, const IdwArgs &a, hipStream_t st);
+
+auv_status launch_bilinear(const float *src, const auv_grid_desc &s, float *dst,
+                           const auv_grid_desc &d, hipStream_t st);
+
+}  // namespace auv
