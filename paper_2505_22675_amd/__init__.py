@@ -273,7 +273,7 @@ def auv_resample_bilinear(src: torch.Tensor, s_desc, dst: torch.Tensor, d_desc, 
 # ------------------------------------------------------------ conveniences --
 
 def grid_idw(grid: Grid, bins: Bins, power=2.0, radius=None, min_pts=1, max_pts=0,
-             with_counts=False, with_nearest=False, stream=None):
+             with_counts=False, with_nearest=False, precision=AUV_P_FP32_REBASE, stream=None):
     """Allocate outputs and run auv_interp_idw; returns a dict of tensors."""
     dev = bins.ws.device
     shape = (grid.ny, grid.nx)
@@ -283,7 +283,8 @@ def grid_idw(grid: Grid, bins: Bins, power=2.0, radius=None, min_pts=1, max_pts=
     if with_nearest:
         out["nn_idx"] = torch.empty(shape, dtype=torch.int32, device=dev)
         out["nn_z"] = torch.empty(shape, dtype=torch.float32, device=dev)
-    p = idw_params(power, bins.radius if radius is None else radius, min_pts, max_pts)
+    p = idw_params(power, bins.radius if radius is None else radius, min_pts, max_pts,
+                   precision)
     auv_interp_idw(grid, bins, p, out["z"], out.get("cnt"), out.get("nn_idx"),
                    out.get("nn_z"), stream)
     return out

@@ -156,6 +156,13 @@ auv_status auv_bin_points(const auv_grid *grid, const double *x, const double *y
     b->v.res = w.res;
     b->v.z = w.z;
     b->v.idx = w.idx;
+    b->v.rec = w.rec;
+    {
+        int bits = 1;
+        while (bits < 31 && (int64_t(1) << bits) < n)
+            ++bits;
+        b->v.idx_bits = bits;
+    }
     b->v.nbx = geom.nbx;
     b->v.nby = geom.nby;
     b->v.halo = geom.halo;
@@ -236,6 +243,11 @@ static auv_status idw_common(const auv_grid *grid, const auv_bins *bins,
     a->nx = grid->d.nx;
     a->ny = grid->d.ny;
     a->R = (int32_t)Rd;
+    a->R_stage = (int32_t)Rd;
+    a->inv_r2 = (float)(1.0 / (Rd * Rd));
+    a->r2f = (float)(radius * radius);
+    a->x0 = grid->d.x0;
+    a->y0 = grid->d.y0;
     return AUV_OK;
 }
 
@@ -250,10 +262,15 @@ auv_status auv_interp_idw(const auv_grid *grid, const auv_bins *bins,
         return fail(AUV_ERR_INVALID, "power must be in (0, 64]");
     if (params->min_pts < 0 || params->max_pts < 0 || params->reserved != 0)
         return fail(AUV_ERR_INVALID, "min_pts/max_pts must be >= 0, reserved 0");
-    if (params->precision != AUV_P_FP32_REBASE)
-        return fail(AUV_ERR_INVALID, "precision variant not available here");
+    if (params->precision < AUV_P_FP32_REBASE || params->precision > AUV_P_FP32_ABSOLUTE)
+        return fail(AUV_ERR_INVALID, "unknown precision variant");
     IdwArgs a;
     AUV_TRY(idw_common(grid, bins, params->radius, &a));
+    if (params->precision != AUV_P_FP32_REBASE) {
+        // the variants' rounded distances may admit soundings slightly beyond
+        // the radius: search one metre further (clamped to the bin domain)
+        a.R_stage = a.R + (int32_t)kLatticePerMetre;
+    }
     AUV_TRY(check_device_ptr(z_out, "z_out"));
     if (cnt_out)
         AUV_TRY(check_device_ptr(cnt_out, "cnt_out"));

@@ -47,7 +47,9 @@ struct auv_bin_view {
     const uint32_t *res;        // packed residuals: low 16 bits x, high 16 bits y
     const float *z;             // depth rounded to float
     const int32_t *idx;         // original index (perm)
+    const int4 *rec;            // per original index: X, Y, residuals, depth bits
     int32_t nbx, nby, halo, bin_log2;
+    int32_t idx_bits;           // bits of the largest original index
     int32_t R;                  // lattice radius the bins were built for
 };
 
@@ -89,6 +91,12 @@ struct BinWorkspace {
     int32_t *idx;
     int64_t *stats;       // [4]
     int32_t *big_list;    // [nb] bins too long for one thread
+    int32_t *row_count;   // [nby] soundings per bin row (row path)
+    int32_t *row_start;   // [nby + 1]
+    int32_t *rowid;       // [n] bin row per input sounding (or -1)
+    unsigned long long *keys;  // [n] (bin column << 32 | original index)
+    unsigned long long *keys2; // [n] scratch for the per-row sort
+    int32_t *drops;            // per-block dropped-sounding counters
     size_t bytes;
 };
 size_t bin_workspace_layout(int64_t n, const BinGeom &g, char *base,
@@ -108,12 +116,29 @@ struct IdwArgs {
     int32_t min_pts, max_pts;
     int32_t precision;
     int32_t mode;             // bit 0: IDW value, bit 1: nearest outputs
+    float inv_r2;             // 1 / R^2 (lattice units)
+    int32_t R_stage;          // lattice reach of the candidate search (>= R)
+    float r2f;                // radius^2 in m^2, FP32 (precision variants)
+    double x0, y0;            // grid origin (precision variants)
     float *z_out;
     int32_t *cnt_out;
     int32_t *nn_idx_out;
     float *nn_z_out;
 };
 auv_status launch_idw(const auv_bin_view &bins, const IdwArgs &a, hipStream_t st);
+
+// Window form of the IDW kernel (linear node lattice, window <= 256 cells).
+struct WinGeom {
+    int DXl, DYl;   // node spacing in lattice units
+    int X0, Y0;     // lattice coordinate of node column 0 / row 0
+    int Wx, Wy;     // nodes per axis a sounding can reach
+    int ncells, nchunks;
+};
+bool window_geometry(const IdwArgs &a, WinGeom *g);
+auv_status launch_idw_window(const auv_bin_view &bins, const IdwArgs &a, const WinGeom &g,
+                             int pmode, hipStream_t st);
+auv_status launch_idw_window_prec(const auv_bin_view &bins, const IdwArgs &a,
+                                  const WinGeom &g, int pmode, hipStream_t st);
 
 auv_status launch_bilinear(const float *src, const auv_grid_desc &s, float *dst,
                            const auv_grid_desc &d, hipStream_t st);

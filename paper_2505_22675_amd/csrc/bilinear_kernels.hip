@@ -1,10 +1,8 @@
 // Bilinear resample of one grid onto another (Sec. III-A of the paper).
 //
-// Each thread produces four consecutive destination nodes of one row and
-// writes them with one 16-byte store when the row allows it.  The source
-// index coordinate of a node is computed in FP64 with the same operations, in
-// the same order, as its definition (no contraction), so the corner choice is
-// exact; the blend itself is FP32 in lerp form (top, bottom, then vertical),
+// The source index coordinate of a node is computed in FP64 with the same
+// operations, in the same order, as its definition (no contraction), so the
+// corner choice is exact; the blend itself is FP32 in lerp form (top, bottom, then vertical),
 // which keeps constants exact and lets a NaN corner propagate: a hole.
 #include "auv_internal.hpp"
 
@@ -42,37 +40,104 @@ struct BilArgs {
     double sx0, sy0, sdx, sdy;
     double dx0, dy0, ddx, ddy;
     int snx, sny, dnx, dny;
-    int groups;  // 4-node groups per destination row
 };
 
-__global__ __launch_bounds__(256) void k_bilinear(BilArgs p)
+constexpr int kBilThreads = 256;
+constexpr int kBilCols = kBilThreads * 4;  // destination columns per block
+constexpr int kBilRows = 8;                // destination rows per block
+constexpr int kBilStage = 6144;            // source values staged in LDS
+
+// One block owns a 1024-column x 8-row patch of the destination.  The FP64
+// axis maps of its columns and rows are computed once into LDS; the source
+// rectangle the patch reads is staged into LDS with coalesced loads when it
+// fits (otherwise corners are gathered from global memory); every thread then
+// produces four consecutive nodes per row with one 16-byte streaming store.
+__global__ __launch_bounds__(kBilThreads) void k_bilinear(BilArgs p)
 {
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t total = (int64_t)p.groups * p.dny;
-    if (g >= total)
+    __shared__ int s_i0[kBilCols], s_i1[kBilCols];
+    __shared__ float s_t[kBilCols];
+    __shared__ int s_j0[kBilRows], s_j1[kBilRows];
+    __shared__ float s_s[kBilRows];
+    __shared__ float s_src[kBilStage];
+    const int col0 = blockIdx.x * kBilCols;
+    const int row0 = blockIdx.y * kBilRows;
+    const int ncol = min(kBilCols, p.dnx - col0);
+    const int nrow = min(kBilRows, p.dny - row0);
+    for (int c = threadIdx.x; c < kBilCols; c += kBilThreads) {
+        const Axis a = axis_of(p.dx0, p.ddx, min(col0 + c, p.dnx - 1), p.sx0, p.sdx, p.snx);
+        s_i0[c] = a.i0;
+        s_i1[c] = a.i1;
+        s_t[c] = a.t;
+    }
+    if (threadIdx.x < kBilRows) {
+        const Axis a = axis_of(p.dy0, p.ddy, min(row0 + (int)threadIdx.x, p.dny - 1), p.sy0,
+                               p.sdy, p.sny);
+        s_j0[threadIdx.x] = a.i0;
+        s_j1[threadIdx.x] = a.i1;
+        s_s[threadIdx.x] = a.t;
+    }
+    __syncthreads();
+    // source rectangle read by the patch (the maps are monotone)
+    const int il = s_i0[0], ih = s_i1[ncol - 1];
+    const int jl = s_j0[0], jh = s_j1[nrow - 1];
+    const int sw = ih - il + 1, sh = jh - jl + 1;
+    const bool staged = (long long)sw * sh <= kBilStage;
+    if (staged) {
+        for (int e = threadIdx.x; e < sw * sh; e += kBilThreads) {
+            const int r = e / sw, c = e - r * sw;
+            s_src[e] = p.src[(int64_t)(jl + r) * p.snx + il + c];
+        }
+        __syncthreads();
+    }
+    const int c = threadIdx.x * 4;
+    if (c >= ncol)
         return;
-    const int row = (int)(g / p.groups);
-    const int c0 = (int)(g - (int64_t)row * p.groups) * 4;
-    const Axis ay = axis_of(p.dy0, p.ddy, row, p.sy0, p.sdy, p.sny);
-    const float *r0 = p.src + (int64_t)ay.i0 * p.snx;
-    const float *r1 = p.src + (int64_t)ay.i1 * p.snx;
-    float v[4];
+    int i0[4], i1[4];
+    float t[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int c = min(c0 + k, p.dnx - 1);
-        const Axis ax = axis_of(p.dx0, p.ddx, c, p.sx0, p.sdx, p.snx);
-        const float q00 = r0[ax.i0], q10 = r0[ax.i1];
-        const float q01 = r1[ax.i0], q11 = r1[ax.i1];
-        const float top = q00 + ax.t * (q10 - q00);
-        const float bot = q01 + ax.t * (q11 - q01);
-        v[k] = top + ay.t * (bot - top);
+        i0[k] = s_i0[c + k];
+        i1[k] = s_i1[c + k];
+        t[k] = s_t[c + k];
     }
-    float *out = p.dst + (int64_t)row * p.dnx + c0;
-    if (c0 + 4 <= p.dnx && ((reinterpret_cast<uintptr_t>(out) & 15) == 0)) {
-        *reinterpret_cast<float4 *>(out) = make_float4(v[0], v[1], v[2], v[3]);
-    } else {
-        for (int k = 0; k < 4 && c0 + k < p.dnx; ++k)
-            out[k] = v[k];
+    const bool vec = c + 4 <= ncol && (p.dnx & 3) == 0 &&
+                     (reinterpret_cast<uintptr_t>(p.dst) & 15) == 0;
+    for (int r = 0; r < nrow; ++r) {
+        const float s = s_s[r];
+        float v[4];
+        if (staged) {
+            const float *r0 = s_src + (s_j0[r] - jl) * sw - il;
+            const float *r1 = s_src + (s_j1[r] - jl) * sw - il;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float q00 = r0[i0[k]], q10 = r0[i1[k]];
+                const float q01 = r1[i0[k]], q11 = r1[i1[k]];
+                const float top = q00 + t[k] * (q10 - q00);
+                const float bot = q01 + t[k] * (q11 - q01);
+                v[k] = top + s * (bot - top);
+            }
+        } else {
+            const float *r0 = p.src + (int64_t)s_j0[r] * p.snx;
+            const float *r1 = p.src + (int64_t)s_j1[r] * p.snx;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float q00 = r0[i0[k]], q10 = r0[i1[k]];
+                const float q01 = r1[i0[k]], q11 = r1[i1[k]];
+                const float top = q00 + t[k] * (q10 - q00);
+                const float bot = q01 + t[k] * (q11 - q01);
+                v[k] = top + s * (bot - top);
+            }
+        }
+        float *out = p.dst + (int64_t)(row0 + r) * p.dnx + col0 + c;
+        if (vec) {
+            // streaming store: the destination is not re-read by this kernel
+            typedef float f4v __attribute__((ext_vector_type(4)));
+            const f4v vv = {v[0], v[1], v[2], v[3]};
+            __builtin_nontemporal_store(vv, reinterpret_cast<f4v *>(out));
+        } else {
+            for (int k = 0; k < 4 && c + k < ncol; ++k)
+                out[k] = v[k];
+        }
     }
 }
 
@@ -96,12 +161,9 @@ auv_status launch_bilinear(const float *src, const auv_grid_desc &s, float *dst,
     p.sny = s.ny;
     p.dnx = d.nx;
     p.dny = d.ny;
-    p.groups = (d.nx + 3) / 4;
-    const int64_t total = (int64_t)p.groups * d.ny;
-    const int64_t blocks = (total + 255) / 256;
-    if (blocks > INT32_MAX)
-        return fail(AUV_ERR_RANGE, "destination grid too large");
-    k_bilinear<<<(unsigned)blocks, 256, 0, st>>>(p);
+    const dim3 grid((unsigned)((d.nx + kBilCols - 1) / kBilCols),
+                    (unsigned)((d.ny + kBilRows - 1) / kBilRows));
+    k_bilinear<<<grid, kBilThreads, 0, st>>>(p);
     AUV_HIP(hipGetLastError());
     return AUV_OK;
 }

@@ -84,8 +84,7 @@ __global__ __launch_bounds__(kThreads) void k_rebase_count(
     const double *__restrict__ z, int64_t n, double x0, double y0, int32_t s,
     int32_t hB, int32_t nbx, double lo, double hix, double hiy,
     int32_t *__restrict__ counts, int32_t *__restrict__ key,
-    int32_t *__restrict__ slot, int4 *__restrict__ rec,
-    unsigned long long *__restrict__ stats)
+    int32_t *__restrict__ slot, int4 *__restrict__ rec, int32_t *__restrict__ drops)
 {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     int bad = 0, out = 0;
@@ -115,12 +114,36 @@ __global__ __launch_bounds__(kThreads) void k_rebase_count(
         key[i] = k;
         slot[i] = sl;
     }
-    const unsigned long long mb = __ballot(bad), mo = __ballot(out);
+    int tb, tob;
+    {
+        __shared__ int lds_b[kThreads / 64];
+        block_exclusive_scan(bad, lds_b, &tb);
+        block_exclusive_scan(out, lds_b, &tob);
+    }
+    if (threadIdx.x == 0) {
+        drops[2 * blockIdx.x] = tb;
+        drops[2 * blockIdx.x + 1] = tob;
+    }
+}
+
+// Sum of the per-block drop counters of k_rebase_count (one block).
+__global__ __launch_bounds__(kThreads) void k_sum_drops(const int32_t *__restrict__ drops,
+                                                        int32_t nblk,
+                                                        unsigned long long *__restrict__ stats)
+{
+    long long nbad = 0, nout = 0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads) {
+        nbad += drops[2 * b];
+        nout += drops[2 * b + 1];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        nbad += __shfl_xor(nbad, d, 64);
+        nout += __shfl_xor(nout, d, 64);
+    }
     if (lane_id() == 0) {
-        if (mb)
-            atomicAdd(&stats[1], (unsigned long long)__popcll(mb));
-        if (mo)
-            atomicAdd(&stats[2], (unsigned long long)__popcll(mo));
+        atomicAdd(&stats[1], (unsigned long long)nbad);
+        atomicAdd(&stats[2], (unsigned long long)nout);
     }
 }
 
@@ -281,6 +304,280 @@ __global__ __launch_bounds__(kThreads) void k_stabilise_big(
     }
 }
 
+// ----------------------------------------------------------- row path ----
+//
+// Two-level counting sort used when the bin rows fit an LDS histogram:
+//   k_row_hist    rebase + per-block LDS histogram over bin rows; one global
+//                 atomic per (block, non-empty row) reserves the block's range
+//   k_row_scan    exclusive scan of the row counts (one block)
+//   k_row_scatter each sounding's (column, index) key into its row's range
+//   k_row_sort    one block per bin row: counting sort by bin column in LDS
+//                 (which also yields the row's cell_start entries), then rank
+//                 each bin's members by original index; write the binned SoA.
+// Device-scope atomics drop from one per sounding to one per block and row.
+
+constexpr int kRowChunk = 1024;          // soundings per block in k_row_hist
+constexpr int kRowPerThread = kRowChunk / kThreads;
+constexpr int kMaxRowsLds = 8192;        // bin rows in the LDS histogram
+
+__global__ __launch_bounds__(kThreads) void k_row_hist(
+    const double *__restrict__ x, const double *__restrict__ y,
+    const double *__restrict__ z, int64_t n, double x0, double y0, int32_t s,
+    int32_t hB, int32_t nby, double lo, double hix, double hiy,
+    int32_t *__restrict__ row_count, int32_t *__restrict__ rowid,
+    int32_t *__restrict__ pos, int32_t *__restrict__ colkey, int4 *__restrict__ rec,
+    int32_t *__restrict__ drops)
+{
+    __shared__ int s_cnt[kMaxRowsLds];
+    for (int r = threadIdx.x; r < nby; r += kThreads)
+        s_cnt[r] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRowChunk + threadIdx.x;
+    int row[kRowPerThread], lr[kRowPerThread];
+    int bad = 0, out = 0;
+#pragma unroll
+    for (int j = 0; j < kRowPerThread; ++j) {
+        const int64_t i = base + (int64_t)j * kThreads;
+        row[j] = -1;
+        lr[j] = 0;
+        if (i < n) {
+            const double xi = x[i], yi = y[i], zi = z[i];
+            if (!(isfinite(xi) && isfinite(yi) && isfinite(zi))) {
+                bad += 1;  // NaN / infinite samples are invalid candidates
+            } else {
+                const double tx = (xi - x0) * kLatticePerMetre;
+                const double ty = (yi - y0) * kLatticePerMetre;
+                const double rx = rint(tx), ry = rint(ty);
+                if (rx >= lo && rx < hix && ry >= lo && ry < hiy) {
+                    const int X = (int)rx, Y = (int)ry;
+                    const int qx = (int)rint((tx - rx) * 32768.0);
+                    const int qy = (int)rint((ty - ry) * 32768.0);
+                    const uint32_t rr = ((uint32_t)qx & 0xffffu) | ((uint32_t)qy << 16);
+                    rec[i] = make_int4(X, Y, (int)rr, __float_as_int((float)zi));
+                    colkey[i] = (X + hB) >> s;
+                    row[j] = (Y + hB) >> s;
+                } else {
+                    out += 1;
+                }
+            }
+        }
+        // Reserve slots in the block's row counters, one LDS atomic per
+        // distinct row in the wave (a ping's beams share a bin row, so
+        // per-lane atomics would serialise on one address).
+        const int rj = row[j];
+        unsigned long long pending = __ballot(rj >= 0);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const int r = __shfl(rj, leader, 64);
+            const unsigned long long grp = __ballot(rj == r) & pending;
+            int b = 0;
+            if (lane_id() == leader)
+                b = atomicAdd(&s_cnt[r], __popcll(grp));
+            b = __shfl(b, leader, 64);
+            if ((grp >> lane_id()) & 1ull)
+                lr[j] = b + __popcll(grp & ((1ull << lane_id()) - 1ull));
+            pending &= ~grp;
+        }
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < nby; r += kThreads) {
+        const int c = s_cnt[r];
+        if (c)
+            s_cnt[r] = atomicAdd(&row_count[r], c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kRowPerThread; ++j) {
+        const int64_t i = base + (int64_t)j * kThreads;
+        if (i < n) {
+            rowid[i] = row[j];
+            pos[i] = row[j] >= 0 ? s_cnt[row[j]] + lr[j] : 0;
+        }
+    }
+    // per-block drop counters (summed by k_row_scan: a device-wide atomic on
+    // one address per wave would serialise at the memory side)
+    int tb, tob;
+    {
+        __shared__ int lds_b[kThreads / 64];
+        block_exclusive_scan(bad, lds_b, &tb);
+        block_exclusive_scan(out, lds_b, &tob);
+    }
+    if (threadIdx.x == 0) {
+        drops[2 * blockIdx.x] = tb;
+        drops[2 * blockIdx.x + 1] = tob;
+    }
+}
+
+// Exclusive scan of the row counts by one block; also the binned total.
+__global__ __launch_bounds__(kThreads) void k_row_scan(
+    const int32_t *__restrict__ cnt, int32_t nby, int32_t *__restrict__ start,
+    const int32_t *__restrict__ drops, int32_t nblk, unsigned long long *__restrict__ stats)
+{
+    __shared__ int lds[kThreads / 64];
+    long long nbad = 0, nout = 0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads) {
+        nbad += drops[2 * b];
+        nout += drops[2 * b + 1];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        nbad += __shfl_xor(nbad, d, 64);
+        nout += __shfl_xor(nout, d, 64);
+    }
+    if (lane_id() == 0) {
+        atomicAdd(&stats[1], (unsigned long long)nbad);
+        atomicAdd(&stats[2], (unsigned long long)nout);
+    }
+    int carry = 0;
+    for (int c = 0; c < nby; c += kThreads) {
+        const int i = c + threadIdx.x;
+        const int v = i < nby ? cnt[i] : 0;
+        int total;
+        const int ex = block_exclusive_scan(v, lds, &total);
+        if (i < nby)
+            start[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) {
+        start[nby] = carry;
+        stats[0] = (unsigned long long)carry;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_row_scatter(
+    const int32_t *__restrict__ rowid, const int32_t *__restrict__ pos,
+    const int32_t *__restrict__ colkey, int64_t n, const int32_t *__restrict__ row_start,
+    unsigned long long *__restrict__ keys)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) {
+        const int r = rowid[i];
+        if (r >= 0)
+            keys[row_start[r] + pos[i]] =
+                ((unsigned long long)(uint32_t)colkey[i] << 32) | (uint32_t)i;
+    }
+}
+
+// Ascending bitonic sort of a[0, n) for any n: the sequence is treated as
+// padded with +inf up to a power of two, and pairs whose upper element lies in
+// the padding are skipped (the mirrored first step of each merge keeps every
+// comparison ascending, so padding never moves).  Whole block, any memory.
+template <class T>
+__device__ void block_bitonic_sort(T *a, int n)
+{
+    int npow = 1;
+    while (npow < n)
+        npow <<= 1;
+    const int pairs = npow >> 1;
+    for (int size = 2; size <= npow; size <<= 1) {
+        const int half = size >> 1;
+        for (int t = threadIdx.x; t < pairs; t += kThreads) {
+            const int blk = t / half, off = t - blk * half;
+            const int i = blk * size + off, j = blk * size + size - 1 - off;
+            if (j < n) {
+                const T u = a[i], v = a[j];
+                if (v < u) {
+                    a[i] = v;
+                    a[j] = u;
+                }
+            }
+        }
+        __threadfence_block();
+        __syncthreads();
+        for (int stride = size >> 2; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < pairs; t += kThreads) {
+                const int blk = t / stride, off = t - blk * stride;
+                const int i = blk * 2 * stride + off, j = i + stride;
+                if (j < n) {
+                    const T u = a[i], v = a[j];
+                    if (v < u) {
+                        a[i] = v;
+                        a[j] = u;
+                    }
+                }
+            }
+            __threadfence_block();
+            __syncthreads();
+        }
+    }
+}
+
+// One block per bin row: counting sort of the row's soundings by bin column
+// (LDS histogram -> exclusive scan = the row's cell_start entries).  Inside a
+// bin, members are ordered by original index: by ranking (rank = number of
+// members with a smaller index) when every bin of the row is small, else by
+// a bitonic sort of the row's (column, index) keys (in LDS when they fit,
+// otherwise in place in the key array).  tmp_keys is scratch of the same size.
+constexpr int kColsLds = 8192;
+constexpr int kSmallRank = 64;      // largest bin ranked member by member
+constexpr int kRowSortLds = 4096;   // keys of a row sorted in LDS
+
+__global__ __launch_bounds__(kThreads) void k_row_sort(
+    unsigned long long *__restrict__ keys, const int32_t *__restrict__ row_start,
+    int32_t nby, int32_t nbx, const int4 *__restrict__ rec, SoA o,
+    int32_t *__restrict__ cell_start, unsigned long long *__restrict__ tmp_keys)
+{
+    __shared__ int s_h[kColsLds];
+    __shared__ unsigned long long s_k[kRowSortLds];
+    __shared__ int lds[kThreads / 64];
+    const int row = blockIdx.x;
+    const int r0 = row_start[row], n = row_start[row + 1] - r0;
+    for (int bx = threadIdx.x; bx < nbx; bx += kThreads)
+        s_h[bx] = 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += kThreads)
+        atomicAdd(&s_h[(int)(keys[r0 + k] >> 32)], 1);
+    __syncthreads();
+    int32_t *cs = cell_start + (int64_t)row * nbx;
+    int carry = 0, big = 0;
+    for (int c = 0; c < nbx; c += kThreads) {
+        const int bx = c + threadIdx.x;
+        const int v = bx < nbx ? s_h[bx] : 0;
+        big |= v > kSmallRank ? 1 : 0;
+        int total;
+        const int ex = block_exclusive_scan(v, lds, &total);
+        if (bx < nbx) {
+            s_h[bx] = carry + ex;  // bin start within the row
+            cs[bx] = r0 + carry + ex;
+        }
+        carry += total;
+    }
+    if (row == nby - 1 && threadIdx.x == 0)
+        cell_start[(int64_t)nby * nbx] = row_start[nby];
+    if (__syncthreads_or(big)) {
+        unsigned long long *a = keys + r0;
+        if (n <= kRowSortLds) {
+            for (int k = threadIdx.x; k < n; k += kThreads)
+                s_k[k] = keys[r0 + k];
+            __syncthreads();
+            a = s_k;
+        }
+        block_bitonic_sort(a, n);
+        for (int k = threadIdx.x; k < n; k += kThreads)
+            emit(o, r0 + k, (int)(uint32_t)(a[k] & 0xffffffffull), rec);
+        return;
+    }
+    // scatter (column, original index) into the bins (unordered inside a
+    // bin); afterwards s_h[bx] is the end of bin bx, i.e. the start of bx+1
+    for (int k = threadIdx.x; k < n; k += kThreads) {
+        const unsigned long long key = keys[r0 + k];
+        const int p = atomicAdd(&s_h[(int)(key >> 32)], 1);
+        tmp_keys[r0 + p] = key;
+    }
+    __threadfence_block();
+    __syncthreads();
+    // one thread per sounding: its rank among its bin's members
+    for (int p = threadIdx.x; p < n; p += kThreads) {
+        const unsigned long long key = tmp_keys[r0 + p];
+        const int bx = (int)(key >> 32);
+        const int b0 = bx == 0 ? 0 : s_h[bx - 1], b1 = s_h[bx];
+        int rank = 0;
+        for (int q = b0; q < b1; ++q)
+            rank += tmp_keys[r0 + q] < key ? 1 : 0;
+        emit(o, r0 + b0 + rank, (int)(uint32_t)(key & 0xffffffffull), rec);
+    }
+}
+
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 inline unsigned grid_for(int64_t n, int threads)
@@ -293,7 +590,11 @@ inline unsigned grid_for(int64_t n, int threads)
 
 int32_t default_bin_log2(int32_t R)
 {
-    int s = 31 - __builtin_clz((unsigned)std::max(R, 1));
+    // smallest power of two not below R: a node's disk meets at most 3 bins
+    // per axis, and bin rows stay few for the row-wise counting sort
+    int s = 0;
+    while (s < 31 && (int64_t(1) << s) < R)
+        ++s;
     return std::min(26, std::max(12, s));
 }
 
@@ -341,7 +642,8 @@ size_t bin_workspace_layout(int64_t n, const BinGeom &g, char *base, BinWorkspac
     t.stats = (int64_t *)take(4 * sizeof(int64_t));
     t.counts = (int32_t *)take(sizeof(int32_t) * nb);
     t.cell_start = (int32_t *)take(sizeof(int32_t) * (nb + 1));
-    t.partials = (int32_t *)take(sizeof(int32_t) * std::max<int64_t>(np, 1));
+    t.partials = (int32_t *)take(
+        sizeof(int32_t) * std::max<int64_t>(std::max<int64_t>(np, 2 * ((n + 1023) / 1024)), 2));
     t.big_list = (int32_t *)take(sizeof(int32_t) * nb);
     t.key = (int32_t *)take(sizeof(int32_t) * m);
     t.slot = (int32_t *)take(sizeof(int32_t) * m);
@@ -352,6 +654,12 @@ size_t bin_workspace_layout(int64_t n, const BinGeom &g, char *base, BinWorkspac
     t.res = (uint32_t *)take(sizeof(uint32_t) * m);
     t.z = (float *)take(sizeof(float) * m);
     t.idx = (int32_t *)take(sizeof(int32_t) * m);
+    t.row_count = (int32_t *)take(sizeof(int32_t) * g.nby);
+    t.row_start = (int32_t *)take(sizeof(int32_t) * (g.nby + 1));
+    t.rowid = (int32_t *)take(sizeof(int32_t) * m);
+    t.keys = (unsigned long long *)take(sizeof(unsigned long long) * m);
+    t.keys2 = (unsigned long long *)take(sizeof(unsigned long long) * m);
+    t.drops = (int32_t *)take(sizeof(int32_t) * 2 * ((m + kThreads - 1) / kThreads + 1));
     t.bytes = off;
     if (w)
         *w = t;
@@ -371,12 +679,33 @@ auv_status launch_binning(const auv_grid *g, const BinGeom &geom, const double *
     auto *stats = reinterpret_cast<unsigned long long *>(w.stats);
 
     k_fill_i64<<<1, 64, 0, st>>>(w.stats, 4);
+    if (geom.nby <= kMaxRowsLds && geom.nbx <= kColsLds) {
+        SoA o{w.X, w.Y, w.res, w.z, w.idx};
+        k_fill_i32<<<(unsigned)std::min<int64_t>(grid_for(geom.nby, kThreads), 64), kThreads,
+                     0, st>>>(w.row_count, geom.nby, 0);
+        const int nblk = n > 0 ? (int)grid_for(n, kRowChunk) : 0;
+        if (n > 0)
+            k_row_hist<<<nblk, kThreads, 0, st>>>(
+                x, y, z, n, g->d.x0, g->d.y0, geom.s, hB, geom.nby, lo, hix, hiy,
+                w.row_count, w.rowid, w.slot, w.key, w.rec, w.partials);
+        k_row_scan<<<1, kThreads, 0, st>>>(w.row_count, geom.nby, w.row_start, w.partials, nblk,
+                                           stats);
+        if (n > 0)
+            k_row_scatter<<<grid_for(n, kThreads), kThreads, 0, st>>>(
+                w.rowid, w.slot, w.key, n, w.row_start, w.keys);
+        k_row_sort<<<(unsigned)geom.nby, kThreads, 0, st>>>(
+            w.keys, w.row_start, geom.nby, geom.nbx, w.rec, o, w.cell_start, w.keys2);
+        AUV_HIP(hipGetLastError());
+        return AUV_OK;
+    }
     k_fill_i32<<<(unsigned)std::min<int64_t>(grid_for(nb, kThreads), 4096), kThreads, 0, st>>>(
         w.counts, nb, 0);
-    if (n > 0)
+    if (n > 0) {
         k_rebase_count<<<grid_for(n, kThreads), kThreads, 0, st>>>(
             x, y, z, n, g->d.x0, g->d.y0, geom.s, hB, geom.nbx, lo, hix, hiy,
-            w.counts, w.key, w.slot, w.rec, stats);
+            w.counts, w.key, w.slot, w.rec, w.drops);
+        k_sum_drops<<<1, kThreads, 0, st>>>(w.drops, (int)grid_for(n, kThreads), stats);
+    }
     k_scan_reduce<<<(unsigned)np, kThreads, 0, st>>>(w.counts, nb, w.partials);
     k_scan_partials<<<1, kThreads, 0, st>>>(w.partials, np);
     k_scan_down<<<(unsigned)np, kThreads, 0, st>>>(w.counts, nb, w.partials,

@@ -366,6 +366,13 @@ auv_status launch_idw(const auv_bin_view &bv, const IdwArgs &a, hipStream_t st)
         pmode = 2;
     else if (a.power == 3.0f)
         pmode = 3;
+    WinGeom wg;
+    if (window_geometry(a, &wg))
+        return launch_idw_window(bv, a, wg, pmode, st);
+    if (a.precision != AUV_P_FP32_REBASE)
+        return fail(AUV_ERR_INVALID,
+                    "precision variants need a node spacing that is a multiple of 2^-15 m "
+                    "and a window of at most 256 nodes");
     const dim3 grid((unsigned)ntiles), block(64);
     switch (a.mode) {
     case 1: k_idw_tile<1><<<grid, block, 0, st>>>(bv, a, ntx, nty, pmode); break;

@@ -1,0 +1,694 @@
+// Radius-limited IDW and nearest pick, window form (gfx950).
+//
+// One 64-lane wavefront owns a 16x16 tile of grid nodes whose accumulators
+// live in LDS.  The binned soundings of the bin rows meeting the tile grown by
+// the radius are staged into LDS (compacted to those whose node window meets
+// the tile).  For each staged sounding the 64 lanes cover its window of nodes
+// (the nodes within +-R of it: at most floor(2R/dX)+1 per axis, <= 64 cells
+// per pass), test membership exactly and update the member nodes'
+// accumulators.  Within one instruction every lane owns a distinct node and
+// soundings are applied in staging order, so the read-modify-write needs no
+// atomics and the result is deterministic.
+//
+// Used when the node lattice is linear (dx * 2^15 and dy * 2^15 integers, so
+// X_b = X_0 + b*DX exactly) and the window has at most 256 cells; the tile
+// kernel in idw_kernels.hip covers every other grid.
+//
+// Exactness as in the tile kernel: membership, ranking and hits on the exact
+// lattice D^2 (FP64-held integers), FP32 distances/weights from lattice
+// offsets plus residuals, FP64 final division.  Sums are relative to one
+// reference depth per tile (a sounding's depth, so a constant field stays
+// exact).  A hit (D^2 == 0) enters with a dominant weight, which yields the
+// mean of the hits; it is recognised at the end by a best key of D^2 == 0.
+// Nodes with more than max_pts members are re-done exactly by the whole wave
+// (bisection on the rank-k key over the node's candidates).
+#pragma once
+#include "auv_internal.hpp"
+
+#include <climits>
+#include <cmath>
+
+namespace auv {
+
+namespace win {
+
+constexpr int kTN = 16;              // tile nodes per side
+constexpr int kNodes = kTN * kTN;    // accumulators per wave
+constexpr int kMaxRows = 64;         // bin rows per staging pass
+constexpr int kMaxChunks = 4;        // window cells <= 64 * kMaxChunks
+constexpr float kHitW = 0x1p80f;     // weight of a coincident sounding
+
+__device__ inline int ceil_div(int v, int d)
+{
+    return v >= 0 ? (v + d - 1) / d : -((-v) / d);
+}
+
+__device__ inline int xcd_tile(int bid, int ntiles)
+{
+    const int xcd = bid & 7, local = bid >> 3;
+    const int q = ntiles >> 3, rem = ntiles & 7;
+    return xcd * q + min(xcd, rem) + local;
+}
+
+// Weights for p = 1, 2, 3 on the squared lattice distance (the common scale
+// cancels in num/den).  The floor only guards an exactly-zero fine offset:
+// real offsets are at least one residual unit (2^-15 lattice) away, and the
+// largest weight (p = 3 at the floor) stays 2^20 below the hit weight.
+__device__ inline float weight_fast(float d2n, int pmode)
+{
+    d2n = fmaxf(d2n, 0x1p-40f);
+    if (pmode == 1)
+        return __builtin_amdgcn_rsqf(d2n);
+    if (pmode == 2)
+        return __builtin_amdgcn_rcpf(d2n);
+    const float r = __builtin_amdgcn_rsqf(d2n);
+    return r * r * r;
+}
+
+__device__ inline float log_weight(float d2n, float power)
+{
+    return -0.5f * power * __builtin_amdgcn_logf(fmaxf(d2n, 0x1p-120f));
+}
+
+__device__ inline float wave_sum(float v)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1)
+        v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+__device__ inline int wave_sum_i(int v)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1)
+        v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+__device__ inline int wave_count(bool p) { return __popcll(__ballot(p)); }
+
+// Best key (D^2, index) and its depth, reduced over the wave.
+__device__ inline void wave_best(double &d2, int &idx, float &z)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double od = __shfl_xor(d2, d, 64);
+        const int oi = __shfl_xor(idx, d, 64);
+        const float oz = __shfl_xor(z, d, 64);
+        if (od < d2 || (od == d2 && oi < idx)) {
+            d2 = od;
+            idx = oi;
+            z = oz;
+        }
+    }
+}
+
+struct Seg {
+    int by_lo, nrows, bx_lo, nbx_row;
+};
+
+// Iterate, wave-wide, over every binned sounding of the bin rows [by_lo,
+// by_lo+nrows) and columns [bx_lo, bx_lo+nbx_row): f(k) per lane with k the
+// binned position, or k = -1 for idle lanes.  Must be called by the whole wave.
+template <class F>
+__device__ inline void for_each_candidate(const auv_bin_view &bv, const Seg &sg, F &&f)
+{
+    const int lane = threadIdx.x;
+    for (int r = 0; r < sg.nrows; ++r) {
+        const int id0 = (sg.by_lo + r) * bv.nbx + sg.bx_lo;
+        const int s = bv.cell_start[id0], e = bv.cell_start[id0 + sg.nbx_row];
+        for (int k0 = s; k0 < e; k0 += 64) {
+            const int k = k0 + lane;
+            f(k < e ? k : -1);
+        }
+    }
+}
+
+// Coordinates of a sounding and of a node under the precision variants, in
+// metres: AUV_P_FP16_OFFSETS rounds offsets from the tile centre to FP16;
+// AUV_P_FP32_ABSOLUTE rounds absolute coordinates to FP32 (no rebase).  The
+// sounding's position is rebuilt from its lattice point and residual.
+__device__ inline void variant_point(const IdwArgs &a, int X, int Y, float rx, float ry,
+                                     int tb0, int ta0, int X0, int Y0, int DXl, int DYl,
+                                     int prec, float *px, float *py)
+{
+    if (prec == AUV_P_FP16_OFFSETS) {
+        // tile centre between its nodes 7 and 8 (DX is even)
+        const int Xc = X0 + tb0 * DXl + (kTN - 1) * (DXl / 2);
+        const int Yc = Y0 + ta0 * DYl + (kTN - 1) * (DYl / 2);
+        *px = (float)(_Float16)(((float)(X - Xc) + rx) * 0x1p-16f);
+        *py = (float)(_Float16)(((float)(Y - Yc) + ry) * 0x1p-16f);
+    } else {
+        *px = (float)(a.x0 + ((double)X + (double)rx) * 0x1p-16);
+        *py = (float)(a.y0 + ((double)Y + (double)ry) * 0x1p-16);
+    }
+}
+
+__device__ inline void variant_node(const IdwArgs &a, int bl, int al, int tb0, int ta0,
+                                    int prec, float *qx, float *qy)
+{
+    if (prec == AUV_P_FP16_OFFSETS) {
+        *qx = (float)(_Float16)(((float)bl - 0.5f * (kTN - 1)) * (float)a.dx);
+        *qy = (float)(_Float16)(((float)al - 0.5f * (kTN - 1)) * (float)a.dy);
+    } else {
+        *qx = (float)(a.x0 + ((double)(tb0 + bl) + 0.5) * a.dx);
+        *qy = (float)(a.y0 + ((double)(ta0 + al) + 0.5) * a.dy);
+    }
+}
+
+// Distance of binned sounding k from node (na, nb) under precision variant
+// kPrec.  Returns the ranking key (exact lattice D^2, or the bit pattern of
+// the variant's FP32 squared distance, both order-preserving and held exactly
+// in a double) and the squared distance in lattice units for the weight.
+template <int kPrec>
+__device__ inline double cand_key(const auv_bin_view &bv, const IdwArgs &a, int k, int Xn,
+                                  int Yn, int na, int nb, int X0, int Y0, int DXl, int DYl,
+                                  float *d2w)
+{
+    const uint32_t res = bv.res[k];
+    const float rx = (float)(int16_t)(res & 0xffffu) * kResidualUnit;
+    const float ry = (float)(int16_t)(res >> 16) * kResidualUnit;
+    if constexpr (kPrec == AUV_P_FP32_REBASE) {
+        const int dX = bv.X[k] - Xn, dY = bv.Y[k] - Yn;
+        const float fx = (float)dX + rx, fy = (float)dY + ry;
+        *d2w = fx * fx + fy * fy;
+        return (double)dX * (double)dX + (double)dY * (double)dY;
+    } else {
+        float px, py, qx, qy;
+        variant_point(a, bv.X[k], bv.Y[k], rx, ry, nb & ~(kTN - 1), na & ~(kTN - 1), X0, Y0,
+                      DXl, DYl, kPrec, &px, &py);
+        variant_node(a, nb & (kTN - 1), na & (kTN - 1), nb & ~(kTN - 1), na & ~(kTN - 1), kPrec,
+                     &qx, &qy);
+        const float ex = px - qx, ey = py - qy;
+        const float d2 = ex * ex + ey * ey;
+        *d2w = d2 * 0x1p32f;
+        return (double)__float_as_uint(d2);
+    }
+}
+
+// Exact value of one over-cap node, computed by the whole wave: find the
+// rank-k key (T, J) by bisection over the key and then over the index among
+// ties, then accumulate the selected set.  Writes the node's outputs.
+template <int kMode, int kPmode, int kPrec>
+__device__ void exact_node(const auv_bin_view &bv, const IdwArgs &a, int X0, int Y0,
+                           int DXl, int DYl, int na, int nb, float zref)
+{
+    const int R = a.R_stage;
+    const double R2 = kPrec == AUV_P_FP32_REBASE ? (double)a.R * (double)a.R
+                                                 : (double)__float_as_uint(a.r2f);
+    const int Xn = X0 + nb * DXl, Yn = Y0 + na * DYl;
+    const int hB = bv.halo << bv.bin_log2;
+    Seg sg;
+    sg.bx_lo = max(0, (Xn - R + hB) >> bv.bin_log2);
+    sg.nbx_row = min(bv.nbx - 1, (Xn + R + hB) >> bv.bin_log2) - sg.bx_lo + 1;
+    sg.by_lo = max(0, (Yn - R + hB) >> bv.bin_log2);
+    sg.nrows = min(bv.nby - 1, (Yn + R + hB) >> bv.bin_log2) - sg.by_lo + 1;
+    auto key_d2 = [&](int k) {
+        float d2w;
+        return cand_key<kPrec>(bv, a, k, Xn, Yn, na, nb, X0, Y0, DXl, DYl, &d2w);
+    };
+    // members only: a key above the radius never counts
+    auto member_key = [&](int k) {
+        const double kv = key_d2(k);
+        return kv <= R2 ? kv : -1.0;
+    };
+    const int kcap = a.max_pts;
+    // smallest T in [0, R2] with #{D^2 <= T} >= k
+    double lo = 0.0, hi = R2;
+    while (lo < hi) {
+        const double mid = floor((lo + hi) * 0.5);
+        int c = 0;
+        for_each_candidate(bv, sg, [&](int k) {
+            const double kv = k >= 0 ? member_key(k) : -1.0;
+            c += wave_count(kv >= 0.0 && kv <= mid);
+        });
+        if (c >= kcap)
+            hi = mid;
+        else
+            lo = mid + 1.0;
+    }
+    const double T = lo;
+    int clt = 0, ceq = 0;
+    for_each_candidate(bv, sg, [&](int k) {
+        const double d2 = k >= 0 ? member_key(k) : -1.0;
+        clt += wave_count(d2 >= 0.0 && d2 < T);
+        ceq += wave_count(d2 >= 0.0 && d2 == T);
+    });
+    const int need = kcap - clt;
+    long long J = INT_MAX;
+    if (ceq > need) {
+        long long jlo = 0, jhi = INT_MAX;
+        while (jlo < jhi) {
+            const long long mid = (jlo + jhi) >> 1;
+            int c = 0;
+            for_each_candidate(bv, sg, [&](int k) {
+                c += wave_count(k >= 0 && member_key(k) == T && bv.idx[k] <= mid);
+            });
+            if (c >= need)
+                jhi = mid;
+            else
+                jlo = mid + 1;
+        }
+        J = jlo;
+    }
+    // accumulate the selected set (per lane, then reduced over the wave)
+    float num = 0.0f, den = 0.0f, emax = -INFINITY;
+    int cnt = 0, hits = 0;
+    double hsum = 0.0, bd2 = 1e300;
+    int bidx = INT_MAX;
+    float bz = 0.0f;
+    for_each_candidate(bv, sg, [&](int k) {
+        if (k < 0)
+            return;
+        float d2f;
+        const double d2 = cand_key<kPrec>(bv, a, k, Xn, Yn, na, nb, X0, Y0, DXl, DYl, &d2f);
+        const int ci = bv.idx[k];
+        if (!(d2 <= R2) || !(d2 < T || (d2 == T && ci <= J)))
+            return;
+        const float z = bv.z[k];
+        cnt += 1;
+        if (d2 < bd2 || (d2 == bd2 && ci < bidx)) {
+            bd2 = d2;
+            bidx = ci;
+            bz = z;
+        }
+        if constexpr ((kMode & 1) != 0) {
+            if (d2 == 0.0) {
+                hits += 1;
+                hsum += (double)z;
+            }
+            if constexpr (kPmode != 0) {
+                const float w = weight_fast(d2f, kPmode);
+                num += w * (z - zref);
+                den += w;
+            } else {
+                const float e = log_weight(d2f * a.inv_r2, a.power);
+                if (e > emax) {
+                    const float sc = __builtin_amdgcn_exp2f(emax - e);
+                    num *= sc;
+                    den *= sc;
+                    emax = e;
+                }
+                const float w = __builtin_amdgcn_exp2f(e - emax);
+                num += w * (z - zref);
+                den += w;
+            }
+        }
+    });
+    cnt = wave_sum_i(cnt);
+    wave_best(bd2, bidx, bz);
+    const int64_t o = (int64_t)na * a.nx + nb;
+    if constexpr ((kMode & 1) != 0) {
+        hits = wave_sum_i(hits);
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1)
+            hsum += __shfl_xor(hsum, d, 64);
+        if constexpr (kPmode == 0) {
+            float em = emax;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1)
+                em = fmaxf(em, __shfl_xor(em, d, 64));
+            const float sc = emax == -INFINITY ? 0.0f : __builtin_amdgcn_exp2f(emax - em);
+            num *= sc;
+            den *= sc;
+        }
+        num = wave_sum(num);
+        den = wave_sum(den);
+    }
+    if (threadIdx.x == 0) {
+        if (kMode & 2) {
+            if (a.nn_idx_out)
+                a.nn_idx_out[o] = bidx;
+            if (a.nn_z_out)
+                a.nn_z_out[o] = bz;
+        }
+        if constexpr ((kMode & 1) != 0) {
+            if (a.cnt_out)
+                a.cnt_out[o] = cnt;
+            float v;
+            if (hits > 0)
+                v = (float)(hsum / (double)hits);
+            else if (cnt < a.min_pts)
+                v = NAN;
+            else
+                v = (float)((double)zref + (double)num / (double)den);
+            a.z_out[o] = v;
+        }
+    }
+}
+
+// LDS accumulators are structure-of-arrays with a padded row stride, so that
+// the 7-row window of one sounding spreads over the banks.
+constexpr int kRS = kTN + 2;
+constexpr int kAcc = kTN * kRS;
+
+// kChunks = window cells / 64 rounded up (compile-time, so the visit loop has
+// no per-chunk branches).  Soundings are never staged in LDS: a 64-wide batch
+// of candidates is tested lane-parallel, and the kept ones are broadcast one
+// by one from their lane (readlane -> SGPRs).  The only LDS traffic in the
+// visit loop is then the fire-and-forget accumulator updates, so nothing in
+// the loop waits on LDS.
+template <int kMode, int kPmode, bool kPacked, int kChunks, int kPrec>
+__global__ __launch_bounds__(64) void k_idw_window(auv_bin_view bv, IdwArgs a, WinGeom g,
+                                                    int ntx, int nty)
+{
+    constexpr bool kIdw = (kMode & 1) != 0;
+    // Accumulators are updated by plain LDS read-modify-write: within one
+    // instruction every lane owns a distinct node, and a wave's LDS operations
+    // complete in order, so no atomics are needed (LDS atomics would serialise
+    // per lane).
+    constexpr bool kAtomic = false;
+    __shared__ float2 s_nd[kAcc];      // numerator, denominator
+    __shared__ int s_cnt[kAcc];
+    __shared__ unsigned long long s_key[kPacked ? kAcc : 1];   // (D^2 << b) | index
+    __shared__ double s_bd2[kPacked ? 1 : kAcc];
+    __shared__ int s_bidx[kPacked ? 1 : kAcc];
+    __shared__ float s_bz[kPacked ? 1 : kAcc];
+    __shared__ float s_emax[kPmode == 0 ? kAcc : 1];
+    __shared__ int s_beg[kMaxRows];
+    __shared__ int s_off[kMaxRows + 1];
+
+    const int lane = threadIdx.x;
+    const int tile = xcd_tile(blockIdx.x, ntx * nty);
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int tb0 = tx * kTN, ta0 = ty * kTN;
+    const int tw = min(kTN, a.nx - tb0), th = min(kTN, a.ny - ta0);
+    const int Xt0 = g.X0 + tb0 * g.DXl, Yt0 = g.Y0 + ta0 * g.DYl;
+    const int R = a.R_stage;          // staging reach (>= the radius)
+    const long long R2 = (long long)a.R * a.R;
+    const int kb = bv.idx_bits;
+    constexpr bool kExact = kPrec == AUV_P_FP32_REBASE;
+
+    // this lane's window cell in each chunk
+    int ci[kChunks], cj[kChunks], iD[kChunks], jD[kChunks], qo[kChunks];
+#pragma unroll
+    for (int t = 0; t < kChunks; ++t) {
+        const int c = t * 64 + lane;
+        const bool v = c < g.ncells;
+        // an unused lane gets a cell far outside any tile
+        ci[t] = v ? c / g.Wx : -100000;
+        cj[t] = v ? c - (c / g.Wx) * g.Wx : -100000;
+        iD[t] = v ? ci[t] * g.DYl : 0;
+        jD[t] = v ? cj[t] * g.DXl : 0;
+        qo[t] = v ? ci[t] * kRS + cj[t] : 0;
+    }
+
+    for (int q = lane; q < kAcc; q += 64) {
+        s_nd[q] = make_float2(0.0f, 0.0f);
+        s_cnt[q] = 0;
+        if constexpr (kPacked) {
+            s_key[q] = ~0ull;
+        } else {
+            s_bd2[q] = 1e300;
+            s_bidx[q] = INT_MAX;
+            s_bz[q] = 0.0f;
+        }
+        if constexpr (kPmode == 0)
+            s_emax[q] = -INFINITY;
+    }
+    __syncthreads();
+
+    // bins covering the tile grown by R
+    const int hB = bv.halo << bv.bin_log2;
+    const int s = bv.bin_log2;
+    const int bx_lo = max(0, (Xt0 - R + hB) >> s);
+    const int nbx_row = min(bv.nbx - 1, (Xt0 + (tw - 1) * g.DXl + R + hB) >> s) - bx_lo + 1;
+    const int by_lo = max(0, (Yt0 - R + hB) >> s);
+    const int nrows = min(bv.nby - 1, (Yt0 + (th - 1) * g.DYl + R + hB) >> s) - by_lo + 1;
+    const float invDX = 1.0f / (float)g.DXl, invDY = 1.0f / (float)g.DYl;
+
+    float zref = 0.0f;
+    bool have_ref = false;
+
+    for (int r0 = 0; r0 < nrows; r0 += kMaxRows) {
+        const int nr = min(kMaxRows, nrows - r0);
+        int beg = 0, len = 0;
+        if (lane < nr) {
+            const int id0 = (by_lo + r0 + lane) * bv.nbx + bx_lo;
+            beg = bv.cell_start[id0];
+            len = bv.cell_start[id0 + nbx_row] - beg;
+        }
+        int inc = len;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int u = __shfl_up(inc, d, 64);
+            if (lane >= d)
+                inc += u;
+        }
+        const int total = __shfl(inc, 63, 64);
+        __syncthreads();
+        if (lane < nr) {
+            s_beg[lane] = beg;
+            s_off[lane] = inc - len;
+        }
+        if (lane == 0)
+            s_off[nr] = total;
+        __syncthreads();
+        for (int c0 = 0; c0 < total; c0 += 64) {
+            const int gi = c0 + lane;
+            bool keep = false;
+            int px = 0, py = 0, pk = 0, pidx = 0;
+            float prx = 0.0f, pry = 0.0f, pz = 0.0f, pvx = 0.0f, pvy = 0.0f;
+            if (gi < total) {
+                int lo = 0, hi = nr - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_off[mid] <= gi)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                const int k = s_beg[lo] + (gi - s_off[lo]);
+                const int xr = bv.X[k] - Xt0, yr = bv.Y[k] - Yt0;
+                // first window column / row: ceil((xr - R) / DX), from a
+                // float estimate corrected exactly in integers
+                int jb = (int)ceilf((float)(xr - R) * invDX);
+                jb += (jb - 1) * g.DXl >= xr - R ? -1 : 0;
+                jb += jb * g.DXl < xr - R ? 1 : 0;
+                int ia = (int)ceilf((float)(yr - R) * invDY);
+                ia += (ia - 1) * g.DYl >= yr - R ? -1 : 0;
+                ia += ia * g.DYl < yr - R ? 1 : 0;
+                keep = jb <= tw - 1 && jb + g.Wx - 1 >= 0 && ia <= th - 1 && ia + g.Wy - 1 >= 0;
+                const uint32_t res = bv.res[k];
+                px = xr - jb * g.DXl;
+                py = yr - ia * g.DYl;
+                prx = (float)(int16_t)(res & 0xffffu) * kResidualUnit;
+                pry = (float)(int16_t)(res >> 16) * kResidualUnit;
+                pz = bv.z[k];
+                pidx = bv.idx[k];
+                if constexpr (!kExact)
+                    variant_point(a, bv.X[k], bv.Y[k], prx, pry, tb0, ta0, g.X0, g.Y0, g.DXl,
+                                  g.DYl, kPrec, &pvx, &pvy);
+                pk = (int)(((uint32_t)ia & 0xffffu) | ((uint32_t)jb << 16));
+            }
+            unsigned long long m = __ballot(keep);
+            if (m == 0ull)
+                continue;
+            if (!have_ref) {
+                // the depth of the first kept sounding is the tile's reference
+                zref = __shfl(pz, __ffsll((long long)m) - 1, 64);
+                have_ref = true;
+            }
+            const float pdz = pz - zref;
+            while (m) {
+                const int l = __ffsll((long long)m) - 1;
+                m &= m - 1ull;
+                const int sx = __builtin_amdgcn_readlane(px, l);
+                const int sy = __builtin_amdgcn_readlane(py, l);
+                const float srx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(prx), l));
+                const float sry = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pry), l));
+                const float sdz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pdz), l));
+                const int sidx = __builtin_amdgcn_readlane(pidx, l);
+                const int spk = __builtin_amdgcn_readlane(pk, l);
+                float svx = 0.0f, svy = 0.0f;
+                if constexpr (!kExact) {
+                    svx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pvx), l));
+                    svy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pvy), l));
+                }
+                const int ia = (int)(int16_t)(spk & 0xffff), jb = spk >> 16;
+                const int qb = ia * kRS + jb;
+#pragma unroll
+                for (int t = 0; t < kChunks; ++t) {
+                    const bool in = (unsigned)(ia + ci[t]) < (unsigned)th &&
+                                    (unsigned)(jb + cj[t]) < (unsigned)tw;
+                    const int dX = sx - jD[t], dY = sy - iD[t];
+                    // ranking key and member test: exact lattice D^2, or the
+                    // variant's FP32 squared distance (bit pattern)
+                    long long D2;
+                    float d2f;
+                    bool mem;
+                    if constexpr (kExact) {
+                        D2 = (long long)dX * dX + (long long)dY * dY;  // exact
+                        mem = in && D2 <= R2;
+                        const float fx = (float)dX + srx, fy = (float)dY + sry;
+                        d2f = fx * fx + fy * fy;
+                    } else {
+                        float qx, qy;
+                        variant_node(a, jb + cj[t], ia + ci[t], tb0, ta0, kPrec, &qx, &qy);
+                        const float ex = svx - qx, ey = svy - qy;
+                        const float dv = ex * ex + ey * ey;
+                        D2 = (long long)__float_as_uint(dv);
+                        mem = in && dv <= a.r2f;
+                        d2f = dv * 0x1p32f;
+                    }
+                    if (mem) {
+                        const int q = qb + qo[t];
+                        float w = 0.0f;
+                        if constexpr (kIdw) {
+                            if constexpr (kPmode != 0)
+                                w = D2 == 0 ? kHitW : weight_fast(d2f, kPmode);
+                            else
+                                w = D2 == 0 ? 1e30f : log_weight(d2f * a.inv_r2, a.power);
+                        }
+                        if constexpr (kAtomic) {
+                            atomicAdd(&s_cnt[q], 1);
+                            atomicMin(&s_key[q], ((unsigned long long)D2 << kb) | (unsigned)sidx);
+                            if constexpr (kIdw) {
+                                atomicAdd(&s_nd[q].x, w * sdz);
+                                atomicAdd(&s_nd[q].y, w);
+                            }
+                        } else {
+                            const int cq = s_cnt[q];
+                            if constexpr (kPacked) {
+                                const unsigned long long key =
+                                    ((unsigned long long)D2 << kb) | (unsigned)sidx;
+                                const unsigned long long kq = s_key[q];
+                                if (key < kq)
+                                    s_key[q] = key;
+                            } else {
+                                const double d2 = (double)D2, bd = s_bd2[q];
+                                if (d2 < bd || (d2 == bd && sidx < s_bidx[q])) {
+                                    s_bd2[q] = d2;
+                                    s_bidx[q] = sidx;
+                                    s_bz[q] = __int_as_float(
+                                        __builtin_amdgcn_readlane(__float_as_int(pz), l));
+                                }
+                            }
+                            s_cnt[q] = cq + 1;
+                            if constexpr (kIdw) {
+                                if constexpr (kPmode != 0) {
+                                    float2 nd = s_nd[q];
+                                    nd.x += w * sdz;
+                                    nd.y += w;
+                                    s_nd[q] = nd;
+                                } else {
+                                    // w holds the log2 weight; rescale to the running max
+                                    float em = s_emax[q];
+                                    float2 nd = s_nd[q];
+                                    if (w > em) {
+                                        const float sc = __builtin_amdgcn_exp2f(em - w);
+                                        nd.x *= sc;
+                                        nd.y *= sc;
+                                        em = w;
+                                        s_emax[q] = em;
+                                    }
+                                    const float lw = __builtin_amdgcn_exp2f(w - em);
+                                    nd.x += lw * sdz;
+                                    nd.y += lw;
+                                    s_nd[q] = nd;
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // finalize: one node per lane, four passes over the tile
+    const int kcap = a.max_pts;
+    const unsigned long long imask = (1ull << kb) - 1ull;
+    for (int q0 = 0; q0 < kTN * kTN; q0 += 64) {
+        const int qq = q0 + lane;
+        const int la = qq / kTN, lb = qq - la * kTN;
+        const int q = la * kRS + lb;
+        const bool act = la < th && lb < tw;
+        const int cnt = s_cnt[q];
+        int bi;
+        bool hit;
+        if constexpr (kPacked) {
+            const unsigned long long key = s_key[q];
+            bi = (int)(key & imask);
+            hit = (key >> kb) == 0ull;
+        } else {
+            bi = s_bidx[q];
+            hit = s_bd2[q] == 0.0;
+        }
+        const bool over = act && kcap > 0 && cnt > kcap;
+        if (act && !over) {
+            const int64_t o = (int64_t)(ta0 + la) * a.nx + tb0 + lb;
+            if (kMode & 2) {
+                if (a.nn_idx_out)
+                    a.nn_idx_out[o] = cnt > 0 ? bi : -1;
+                if (a.nn_z_out) {
+                    float bz;
+                    if constexpr (kPacked)
+                        bz = cnt > 0 ? __int_as_float(bv.rec[bi].w) : NAN;
+                    else
+                        bz = cnt > 0 ? s_bz[q] : NAN;
+                    a.nn_z_out[o] = bz;
+                }
+            }
+            if constexpr (kIdw) {
+                if (a.cnt_out)
+                    a.cnt_out[o] = cnt;
+                // a hit (best D^2 == 0) carries a dominant weight, so the
+                // ratio is the mean of the hits, and it beats min_pts
+                const bool hole = cnt == 0 || (cnt < a.min_pts && !hit);
+                const float2 nd = s_nd[q];
+                a.z_out[o] = hole ? NAN : (float)((double)zref + (double)nd.x / (double)nd.y);
+            }
+        }
+        unsigned long long om = __ballot(over);
+        while (om) {
+            const int l = __ffsll((long long)om) - 1;
+            om &= om - 1;
+            const int qn = q0 + l;
+            exact_node<kMode, kPmode, kPrec>(bv, a, g.X0, g.Y0, g.DXl, g.DYl, ta0 + qn / kTN,
+                                             tb0 + qn % kTN, zref);
+        }
+    }
+}
+
+template <int kMode, bool kPacked, int kChunks, int kPrec>
+void launch_chunks(const auv_bin_view &bv, const IdwArgs &a, const WinGeom &g, int ntx,
+                   int nty, int pmode, hipStream_t st)
+{
+    const dim3 grid((unsigned)(ntx * nty)), block(64);
+    switch (pmode) {
+    case 1: k_idw_window<kMode, 1, kPacked, kChunks, kPrec><<<grid, block, 0, st>>>(bv, a, g, ntx, nty); break;
+    case 2: k_idw_window<kMode, 2, kPacked, kChunks, kPrec><<<grid, block, 0, st>>>(bv, a, g, ntx, nty); break;
+    case 3: k_idw_window<kMode, 3, kPacked, kChunks, kPrec><<<grid, block, 0, st>>>(bv, a, g, ntx, nty); break;
+    default: k_idw_window<kMode, 0, kPacked, kChunks, kPrec><<<grid, block, 0, st>>>(bv, a, g, ntx, nty); break;
+    }
+}
+
+template <int kMode, bool kPacked, int kPrec>
+void launch_mode(const auv_bin_view &bv, const IdwArgs &a, const WinGeom &g, int ntx,
+                 int nty, int pmode, hipStream_t st)
+{
+    switch (g.nchunks) {
+    case 1: launch_chunks<kMode, kPacked, 1, kPrec>(bv, a, g, ntx, nty, pmode, st); break;
+    case 2: launch_chunks<kMode, kPacked, 2, kPrec>(bv, a, g, ntx, nty, pmode, st); break;
+    case 3: launch_chunks<kMode, kPacked, 3, kPrec>(bv, a, g, ntx, nty, pmode, st); break;
+    default: launch_chunks<kMode, kPacked, 4, kPrec>(bv, a, g, ntx, nty, pmode, st); break;
+    }
+}
+
+template <int kMode, int kPrec>
+void launch_mode(const auv_bin_view &bv, const IdwArgs &a, const WinGeom &g, int ntx,
+                 int nty, int pmode, hipStream_t st)
+{
+    // the (D^2, index) key fits 64 bits when R^2 * 2^idx_bits < 2^64
+    const unsigned __int128 top = (unsigned __int128)((unsigned long long)a.R * a.R)
+                                  << bv.idx_bits;
+    if (top < ((unsigned __int128)1 << 64))
+        launch_mode<kMode, true, kPrec>(bv, a, g, ntx, nty, pmode, st);
+    else
+        launch_mode<kMode, false, kPrec>(bv, a, g, ntx, nty, pmode, st);
+}
+
+}  // namespace win
+}  // namespace auv

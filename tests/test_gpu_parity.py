@@ -288,3 +288,85 @@ def test_bilinear_cfg2_upsample(ag, orc, cfg2_run):
         ok = ~np.isnan(ref)
         if ok.any():
             assert np.max(np.abs(o[ok] - ref[ok]) / np.abs(ref[ok])) <= REL
+
+
+# ------------------------------------------------------- dispatch branches --
+
+@pytest.mark.parametrize("dx,radius,kcap", [
+    (1000.0 / 255.0, 9.0, 0),    # node lattice not linear -> tile kernel
+    (0.5, 3.9, 6),               # 16 x 16 window, four lane chunks
+    (0.25, 6.0, 9),              # window too wide -> tile kernel
+    (3.90625, 20.0, 0),          # 11 x 11 window, two lane chunks
+])
+def test_idw_dispatch_branches(ag, orc, dx, radius, kcap):
+    from gen import GridSpec, Soundings
+    nodes = int(min(300, 160.0 / dx))
+    rng = np.random.default_rng(int(dx * 1000) + int(radius))
+    ext = nodes * dx
+    n = int(ext * ext * 0.08) + 500
+    x = rng.uniform(-radius, ext + radius, n) + 123.0
+    y = rng.uniform(-radius, ext + radius, n) - 45.0
+    z = -4000.0 - 50.0 * np.sin(x / 37.0) + rng.normal(0, 2.0, n)
+    g = GridSpec(123.0, -45.0, dx, dx, nodes, nodes - 3)
+    s = Soundings(x, y, z, g, radius=radius, power=2.0, min_pts=2, max_pts=kcap)
+    res, _, _ = _run_idw(ag, s)
+    oz, oc, on = orc.idw(_ogrid(orc, g), x, y, z, radius, 2.0, 2, kcap,
+                         bin_log2=18 if radius < 10 else 20)
+    _assert_idw_equal(res["z"], res["cnt"], res["nn_idx"], res["nn_z"], oz, oc, on, z,
+                      f"dx={dx} r={radius}")
+
+
+def test_binning_many_rows_fallback(ag, orc):
+    """More than 8192 bin rows takes the per-sounding atomic counting sort."""
+    x, y, z, g = uniform_field(n=30000, seed=59, extent=700.0, nodes=175)
+    grid = ag.auv_grid_create(g)
+    bins = ag.auv_bin_points(grid, _dev(x), _dev(y), _dev(z), 1.0, 12)
+    nbx, nby, halo, used = ag.auv_bins_info(bins)
+    assert nby > 8192
+    cs, perm, counts = ag.auv_bins_export(bins)
+    ocs, operm, _, _ = orc.bin_points(_ogrid(orc, g), x, y, z, 1.0, 12)
+    assert np.array_equal(cs.cpu().numpy(), ocs)
+    assert np.array_equal(perm.cpu().numpy(), operm)
+    out = ag.grid_idw(grid, bins, power=2.0, radius=1.0, with_counts=True, with_nearest=True)
+    torch.cuda.synchronize()
+    oz, oc, on = orc.idw(_ogrid(orc, g), x, y, z, 1.0, 2.0, 1, 0, bin_log2=16)
+    _assert_idw_equal(out["z"].cpu().numpy(), out["cnt"].cpu().numpy(),
+                      out["nn_idx"].cpu().numpy(), out["nn_z"].cpu().numpy(), oz, oc, on, z,
+                      "fallback bins")
+
+
+# ----------------------------------------------------- precision variants --
+
+def _variant_errors(ag, orc, s, precision):
+    grid = ag.auv_grid_create(s.grid)
+    bins = ag.auv_bin_points(grid, _dev(s.x), _dev(s.y), _dev(s.z), s.radius, 0)
+    out = ag.grid_idw(grid, bins, power=s.power, min_pts=s.min_pts, max_pts=s.max_pts,
+                      with_counts=True, precision=precision)
+    torch.cuda.synchronize()
+    gz = out["z"].cpu().numpy().astype(np.float64)
+    oz, oc, on = orc.idw(_ogrid(orc, s.grid), s.x, s.y, s.z, s.radius, s.power, s.min_pts,
+                         s.max_pts, bin_log2=19)
+    both = ~np.isnan(gz) & ~np.isnan(oz)
+    err = np.abs(gz[both] - oz[both])
+    return {"max_abs": float(err.max()), "max_rel": float((err / np.abs(oz[both])).max()),
+            "nan_mismatch": int((np.isnan(gz) != np.isnan(oz)).sum()),
+            "count_mismatch": int((out["cnt"].cpu().numpy() != oc).sum()), "n": int(both.sum())}
+
+
+def test_precision_variants_at_utm_scale(ag, orc):
+    """cfg4-style input: absolute UTM-like coordinates (easting ~5e5, northing
+    ~4e6).  The FP64-rebase path keeps the exact contract; the FP16-offset and
+    FP32-absolute variants are measured against the oracle."""
+    s = small_swath(nodes=256, pings=120, beams=100, n_lines=3, seed=60,
+                    x0=500000.0, y0=4000000.0, max_pts=16)
+    exact = _variant_errors(ag, orc, s, ag.AUV_P_FP32_REBASE)
+    assert exact["max_rel"] <= 1e-5 and exact["nan_mismatch"] == 0
+    assert exact["count_mismatch"] == 0
+    fp16 = _variant_errors(ag, orc, s, ag.AUV_P_FP16_OFFSETS)
+    fp32abs = _variant_errors(ag, orc, s, ag.AUV_P_FP32_ABSOLUTE)
+    print("precision errors", exact, fp16, fp32abs)
+    # FP16 offsets (tiles of 32 m): ~1 cm position error, close to the oracle
+    assert fp16["max_abs"] < 5.0 and fp16["n"] > 0.9 * exact["n"]
+    # FP32 absolute: 0.25-0.5 m coordinate ulps, gross but bounded errors
+    assert fp32abs["n"] > 0.8 * exact["n"]
+    assert fp32abs["count_mismatch"] > fp16["count_mismatch"]
