@@ -35,16 +35,140 @@ def host_threads() -> int:
     return len(os.sched_getaffinity(0))
 
 
+def kernel_source_digest() -> str:
+    """Digest of the HIP sources, to tell whether a committed counter profile
+    still describes the kernels being timed."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2505_22675_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        if fn.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, fn), "rb") as f:
+                h.update(fn.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the copy-kernel calibration).
+    None when there is no summary or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_swath2M.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    digest = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("source_digest:"):
+                digest = line.split(":", 1)[1].strip()
+            if line.startswith("traffic_bytes "):
+                _, name, val = line.split()
+                rec[name] = int(val)
+    if digest != kernel_source_digest():
+        return None
+    return rec.get(kernel)
+
+
+def cpu_baseline(s, up_desc, nodes):
+    """The FP64 oracle timed on the host's cores over the same step (binned IDW
+    + nearest on every node, then the bilinear 2x), repeated until at least 10 s
+    of CPU work has run; value = grid nodes per second of the mean repetition."""
+    import oracle
+    oracle.build(force=False)
+    th = host_threads()
+    og = oracle.Grid(s.grid.x0, s.grid.y0, s.grid.dx, s.grid.dy, s.grid.nx, s.grid.ny)
+    ug = oracle.Grid(up_desc.x0, up_desc.y0, up_desc.dx, up_desc.dy, up_desc.nx, up_desc.ny)
+    log(f"cpu baseline: FP64 oracle, binned search, {th} threads, full grid")
+    reps, t_idw, t_bil = 0, 0.0, 0.0
+    while reps < 200 and (t_idw + t_bil < 10.0 or reps == 0):
+        c0 = time.perf_counter()
+        oz, _, _ = oracle.idw(og, s.x, s.y, s.z, s.radius, s.power, s.min_pts, s.max_pts,
+                              bin_log2=19, nthreads=th)
+        c1 = time.perf_counter()
+        oracle.bilinear(og, oz, ug, nthreads=th)
+        c2 = time.perf_counter()
+        t_idw += c1 - c0
+        t_bil += c2 - c1
+        reps += 1
+    per = (t_idw + t_bil) / reps
+    out = {"value": round(nodes / per, 1), "unit": "grid nodes/s", "cores": th,
+           "kind": "oracle",
+           "sample": f"the full step repeated {reps} times ({t_idw + t_bil:.1f} s): binned "
+                     f"FP64 IDW+nearest on all {nodes} nodes ({t_idw / reps:.3f} s each) + "
+                     f"bilinear to 8192^2 ({t_bil / reps:.3f} s each)"}
+    log(f"cpu baseline {out['value']:.3e} nodes/s over {reps} repetitions")
+    return out
+
+
+def precision_report(ag, dev):
+    """The same swath at UTM-scale coordinates (easting 5e5, northing 4e6): each
+    precision variant of the IDW against the FP64 oracle, plus its kernel time."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from gen import workload_cfg4
+
+    log("precision variants on UTM-scale coordinates")
+    s = workload_cfg4()
+    og = oracle.Grid(s.grid.x0, s.grid.y0, s.grid.dx, s.grid.dy, s.grid.nx, s.grid.ny)
+    oz, oc, _ = oracle.idw(og, s.x, s.y, s.z, s.radius, s.power, s.min_pts, s.max_pts,
+                           bin_log2=19, nthreads=host_threads())
+    grid = ag.auv_grid_create(s.grid)
+    x, y, z = (torch.from_numpy(a).to(dev) for a in (s.x, s.y, s.z))
+    bins = ag.auv_bin_points(grid, x, y, z, s.radius, 0)
+    out = {}
+    names = {ag.AUV_P_FP32_REBASE: "fp64_rebase_fp32", ag.AUV_P_FP16_OFFSETS: "fp16_offsets",
+             ag.AUV_P_FP32_ABSOLUTE: "fp32_absolute"}
+    for prec, name in names.items():
+        res = ag.grid_idw(grid, bins, power=s.power, min_pts=s.min_pts, max_pts=s.max_pts,
+                          with_counts=True, precision=prec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            ag.grid_idw(grid, bins, power=s.power, min_pts=s.min_pts, max_pts=s.max_pts,
+                        with_counts=True, precision=prec)
+        e1.record()
+        torch.cuda.synchronize()
+        gz = res["z"].cpu().numpy().astype(np.float64)
+        both = ~np.isnan(gz) & ~np.isnan(oz)
+        err = np.abs(gz[both] - oz[both])
+        rel = err / np.abs(oz[both])
+        out[name] = {"max_abs_m": float(err.max()), "rms_m": float(np.sqrt((err ** 2).mean())),
+                     "max_rel": float(rel.max()),
+                     "nan_mask_mismatch": int((np.isnan(gz) != np.isnan(oz)).sum()),
+                     "count_mismatch": int((res["cnt"].cpu().numpy() != oc).sum()),
+                     "idw_ms": round(e0.elapsed_time(e1) / 5, 4)}
+        log(f"  {name}: {out[name]}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the UTM-scale precision-variant error report")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4}))
+        return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the path shards by spatial tile, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: "
+              "this build runs on a single GPU (the path would shard by spatial tile "
+              "with an r-halo)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -116,31 +240,21 @@ def main():
     dur = {"idw": st_ms[1], "bilinear": st_ms[2]}
     dom = max(dur, key=dur.get)
     achieved = alg[dom] / (dur[dom] * 1e-3) / 1e9
-    kernel_names = {"idw": "k_idw_tile<3>", "bilinear": "k_bilinear"}
+    kernel_names = {"idw": "k_idw_window", "bilinear": "k_bilinear"}
     roofline = {"bound": "hbm", "kernel": kernel_names[dom], "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None, "algorithmic_bytes": int(alg[dom]),
                 "avg_launch_ms": round(float(dur[dom]), 5)}
 
+    roofline["traffic"] = traffic_from_profile(kernel_names[dom])
+
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        oracle.build(force=False)
-        th = host_threads()
-        og = oracle.Grid(s.grid.x0, s.grid.y0, s.grid.dx, s.grid.dy, s.grid.nx, s.grid.ny)
-        ug = oracle.Grid(up_desc.x0, up_desc.y0, up_desc.dx, up_desc.dy, up_desc.nx, up_desc.ny)
-        log(f"cpu baseline: FP64 oracle, binned search, {th} threads, full grid")
-        c0 = time.perf_counter()
-        oz, _, _ = oracle.idw(og, s.x, s.y, s.z, s.radius, s.power, s.min_pts, s.max_pts,
-                              bin_log2=19, nthreads=th)
-        c1 = time.perf_counter()
-        oracle.bilinear(og, oz, ug, nthreads=th)
-        c2 = time.perf_counter()
-        cpu = {"value": round(nodes / (c2 - c0), 1), "unit": "grid nodes/s", "cores": th,
-               "kind": "oracle",
-               "sample": f"full step once: binned FP64 IDW+nearest on all {nodes} nodes "
-                         f"({c1 - c0:.2f} s) + bilinear to 8192^2 ({c2 - c1:.2f} s)"}
-        log(f"cpu baseline {cpu['value']:.3e} nodes/s")
+        cpu = cpu_baseline(s, up_desc, nodes)
+
+    precision = None
+    if not args.no_precision:
+        precision = precision_report(ag, dev)
 
     value = nodes / (ms_per_step * 1e-3)
     rec = {
@@ -157,6 +271,7 @@ def main():
                       "bilinear": round(float(st_ms[2]), 5)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "precision_utm": precision,
     }
     print(json.dumps(rec), flush=True)
 

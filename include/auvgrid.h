@@ -82,8 +82,18 @@ typedef struct {
     int32_t max_pts; /* cap k on the selected set, 0 = no cap                */
     int32_t precision; /* AUV_P_*; only AUV_P_FP32_REBASE meets the exact
                           lattice contract, the others are measured variants */
-    int32_t reserved;  /* must be 0 */
+    int32_t algo;      /* AUV_ALGO_*: kernel form; every form computes the same
+                          result, they differ only in speed */
 } auv_idw_params;
+
+/* Kernel forms of auv_interp_idw. */
+enum {
+    AUV_ALGO_AUTO = 0,   /* dense form when the expected disk population is at
+                            least max_pts (and 1 <= max_pts <= 32), else sparse */
+    AUV_ALGO_SPARSE = 1, /* node windows scattered from each sounding */
+    AUV_ALGO_DENSE = 2   /* per-node ring search with a register top-k list;
+                            needs 1 <= max_pts <= 32 and AUV_P_FP32_REBASE */
+};
 
 /* Library version string (static storage). */
 const char *auv_version(void);
@@ -99,8 +109,8 @@ void auv_grid_destroy(auv_grid *grid);
 
 /* Size in bytes of the device workspace auv_bin_points needs for n soundings,
  * a search radius (metres) and a bin size of 2^bin_log2 lattice units
- * (bin_log2 in [12, 26]; 0 picks the default: the largest power of two not
- * above the radius, clamped to that range). */
+ * (bin_log2 in [12, 26]; 0 picks the default: the smallest power of two not
+ * below the radius, clamped to that range). */
 auv_status auv_bin_workspace_size(const auv_grid *grid, int64_t n, double radius,
                                   int32_t bin_log2, size_t *bytes);
 

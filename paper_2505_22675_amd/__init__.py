@@ -28,6 +28,10 @@ AUV_P_FP32_REBASE = 0
 AUV_P_FP16_OFFSETS = 1
 AUV_P_FP32_ABSOLUTE = 2
 
+AUV_ALGO_AUTO = 0
+AUV_ALGO_SPARSE = 1
+AUV_ALGO_DENSE = 2
+
 
 class AuvError(RuntimeError):
     def __init__(self, status: int, msg: str):
@@ -44,7 +48,7 @@ class auv_grid_desc(ctypes.Structure):
 class auv_idw_params(ctypes.Structure):
     _fields_ = [("power", ctypes.c_double), ("radius", ctypes.c_double),
                 ("min_pts", ctypes.c_int32), ("max_pts", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("algo", ctypes.c_int32)]
 
 
 _lib = None
@@ -231,9 +235,10 @@ def auv_bins_export(bins: Bins, stream=None):
     return cs, perm[:nb], (counts[0], counts[1], counts[2])
 
 
-def idw_params(power=2.0, radius=6.0, min_pts=1, max_pts=0, precision=AUV_P_FP32_REBASE):
+def idw_params(power=2.0, radius=6.0, min_pts=1, max_pts=0, precision=AUV_P_FP32_REBASE,
+               algo=AUV_ALGO_AUTO):
     return auv_idw_params(float(power), float(radius), int(min_pts), int(max_pts),
-                          int(precision), 0)
+                          int(precision), int(algo))
 
 
 def auv_interp_idw(grid: Grid, bins: Bins, params: auv_idw_params, z_out: torch.Tensor,
@@ -273,7 +278,8 @@ def auv_resample_bilinear(src: torch.Tensor, s_desc, dst: torch.Tensor, d_desc, 
 # ------------------------------------------------------------ conveniences --
 
 def grid_idw(grid: Grid, bins: Bins, power=2.0, radius=None, min_pts=1, max_pts=0,
-             with_counts=False, with_nearest=False, precision=AUV_P_FP32_REBASE, stream=None):
+             with_counts=False, with_nearest=False, precision=AUV_P_FP32_REBASE,
+             algo=AUV_ALGO_AUTO, stream=None):
     """Allocate outputs and run auv_interp_idw; returns a dict of tensors."""
     dev = bins.ws.device
     shape = (grid.ny, grid.nx)
@@ -284,7 +290,7 @@ def grid_idw(grid: Grid, bins: Bins, power=2.0, radius=None, min_pts=1, max_pts=
         out["nn_idx"] = torch.empty(shape, dtype=torch.int32, device=dev)
         out["nn_z"] = torch.empty(shape, dtype=torch.float32, device=dev)
     p = idw_params(power, bins.radius if radius is None else radius, min_pts, max_pts,
-                   precision)
+                   precision, algo)
     auv_interp_idw(grid, bins, p, out["z"], out.get("cnt"), out.get("nn_idx"),
                    out.get("nn_z"), stream)
     return out

@@ -260,8 +260,10 @@ auv_status auv_interp_idw(const auv_grid *grid, const auv_bins *bins,
         return fail(AUV_ERR_INVALID, "params is null");
     if (!(params->power > 0.0) || !(params->power <= 64.0))
         return fail(AUV_ERR_INVALID, "power must be in (0, 64]");
-    if (params->min_pts < 0 || params->max_pts < 0 || params->reserved != 0)
-        return fail(AUV_ERR_INVALID, "min_pts/max_pts must be >= 0, reserved 0");
+    if (params->min_pts < 0 || params->max_pts < 0)
+        return fail(AUV_ERR_INVALID, "min_pts/max_pts must be >= 0");
+    if (params->algo < AUV_ALGO_AUTO || params->algo > AUV_ALGO_DENSE)
+        return fail(AUV_ERR_INVALID, "unknown algo");
     if (params->precision < AUV_P_FP32_REBASE || params->precision > AUV_P_FP32_ABSOLUTE)
         return fail(AUV_ERR_INVALID, "unknown precision variant");
     IdwArgs a;
@@ -283,6 +285,20 @@ auv_status auv_interp_idw(const auv_grid *grid, const auv_bins *bins,
     a.max_pts = params->max_pts;
     a.precision = params->precision;
     a.mode = (nn_idx_out || nn_z_out) ? 3 : 1;
+    {
+        // expected soundings per disk, from the input count over the grid
+        // grown by the radius
+        const double r = params->radius;
+        const double area = (grid->d.nx * grid->d.dx + 2 * r) * (grid->d.ny * grid->d.dy + 2 * r);
+        const double lambda = (double)bins->n / area * 3.141592653589793 * r * r;
+        const bool dense_ok = params->max_pts >= 1 && params->max_pts <= 32 &&
+                              params->precision == AUV_P_FP32_REBASE;
+        if (params->algo == AUV_ALGO_DENSE && !dense_ok)
+            return fail(AUV_ERR_INVALID,
+                        "the dense form needs 1 <= max_pts <= 32 and AUV_P_FP32_REBASE");
+        a.dense = params->algo == AUV_ALGO_DENSE ||
+                  (params->algo == AUV_ALGO_AUTO && dense_ok && lambda >= params->max_pts);
+    }
     a.z_out = z_out;
     a.cnt_out = cnt_out;
     a.nn_idx_out = nn_idx_out;

@@ -120,6 +120,7 @@ struct IdwArgs {
     int32_t R_stage;          // lattice reach of the candidate search (>= R)
     float r2f;                // radius^2 in m^2, FP32 (precision variants)
     double x0, y0;            // grid origin (precision variants)
+    bool dense;               // use the dense (ring search, top-k) form
     float *z_out;
     int32_t *cnt_out;
     int32_t *nn_idx_out;
@@ -137,6 +138,8 @@ struct WinGeom {
 bool window_geometry(const IdwArgs &a, WinGeom *g);
 auv_status launch_idw_window(const auv_bin_view &bins, const IdwArgs &a, const WinGeom &g,
                              int pmode, hipStream_t st);
+auv_status launch_idw_dense(const auv_bin_view &bins, const IdwArgs &a, int pmode,
+                            hipStream_t st);
 auv_status launch_idw_window_prec(const auv_bin_view &bins, const IdwArgs &a,
                                   const WinGeom &g, int pmode, hipStream_t st);
 

@@ -366,6 +366,8 @@ auv_status launch_idw(const auv_bin_view &bv, const IdwArgs &a, hipStream_t st)
         pmode = 2;
     else if (a.power == 3.0f)
         pmode = 3;
+    if (a.dense)
+        return launch_idw_dense(bv, a, pmode, st);
     WinGeom wg;
     if (window_geometry(a, &wg))
         return launch_idw_window(bv, a, wg, pmode, st);

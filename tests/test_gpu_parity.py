@@ -370,3 +370,41 @@ def test_precision_variants_at_utm_scale(ag, orc):
     # FP32 absolute: 0.25-0.5 m coordinate ulps, gross but bounded errors
     assert fp32abs["n"] > 0.8 * exact["n"]
     assert fp32abs["count_mismatch"] > fp16["count_mismatch"]
+
+
+# ------------------------------------------------------------- dense form --
+
+@pytest.mark.parametrize("kcap,power,min_pts,snap,bin_log2", [
+    (16, 2.0, 1, 0.0, 15), (16, 1.0, 3, 0.0, 0), (32, 3.0, 1, 0.0, 15),
+    (5, 2.5, 2, 0.25, 14), (1, 2.0, 1, 0.125, 15)])
+def test_idw_dense_form_parity(ag, orc, kcap, power, min_pts, snap, bin_log2):
+    """Dense soundings (hundreds per disk) with a small cap: the ring-search
+    top-k form must select exactly the oracle's k nearest (ties included)."""
+    from gen import GridSpec, Soundings
+    rng = np.random.default_rng(61 + kcap)
+    g = GridSpec(3000.0, -2000.0, 2.0, 2.0, 70, 45)     # ragged 8x8 tiles
+    n = 40000
+    x = g.x0 + rng.uniform(-6, 146, n)
+    y = g.y0 + rng.uniform(-6, 96, n)
+    if snap:
+        x = g.x0 + np.round((x - g.x0) / snap) * snap
+        y = g.y0 + np.round((y - g.y0) / snap) * snap
+    z = -4500.0 + 30.0 * np.sin((x - g.x0) / 17.0) + rng.normal(0, 5.0, n)
+    s = Soundings(x, y, z, g, radius=6.0, power=power, min_pts=min_pts, max_pts=kcap)
+    grid = ag.auv_grid_create(g)
+    bins = ag.auv_bin_points(grid, _dev(x), _dev(y), _dev(z), 6.0, bin_log2)
+    out = ag.grid_idw(grid, bins, power=power, min_pts=min_pts, max_pts=kcap,
+                      with_counts=True, with_nearest=True, algo=ag.AUV_ALGO_DENSE)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    oz, oc, on = orc.idw(_ogrid(orc, g), x, y, z, 6.0, power, min_pts, kcap, bin_log2=18)
+    _assert_idw_equal(res["z"], res["cnt"], res["nn_idx"], res["nn_z"], oz, oc, on, z,
+                      f"dense k={kcap}")
+    assert (oc == kcap).mean() > 0.95
+    # the sparse form (window + exact per-node selection) gives the same result
+    out2 = ag.grid_idw(grid, bins, power=power, min_pts=min_pts, max_pts=kcap,
+                       with_counts=True, with_nearest=True, algo=ag.AUV_ALGO_SPARSE)
+    torch.cuda.synchronize()
+    _assert_idw_equal(out2["z"].cpu().numpy(), out2["cnt"].cpu().numpy(),
+                      out2["nn_idx"].cpu().numpy(), out2["nn_z"].cpu().numpy(), oz, oc, on, z,
+                      f"sparse on dense k={kcap}")
