@@ -192,6 +192,69 @@ auv_status auv_resample_bilinear(const float *src, const auv_grid_desc *s,
                                  float *dst, const auv_grid_desc *d,
                                  auv_stream stream);
 
+/* ------------------------------------------------------------ batches --
+ * Many independent, uneven gridding problems ("items") run as one unit: one
+ * set of batched binning launches and one persistent IDW launch per kernel
+ * form (sparse window, dense top-k; on two concurrent graph branches) whose
+ * waves pull (item, tile) work from per-XCD queues, captured once into a HIP
+ * graph and replayed on later launches.  Bin sizes and the kernel form per item come
+ * from an autotune table (auv_batch_autotune) or from defaults.  Each item's
+ * result is the auv_interp_idw result for that item (same definition and
+ * tolerance); the batch only changes how the work is scheduled. */
+typedef struct {
+    auv_grid_desc grid;
+    const double *x, *y, *z; /* device float64 [n] */
+    int64_t n;
+    auv_idw_params params;   /* precision must be AUV_P_FP32_REBASE */
+    float *z_out;            /* device float [ny][nx] */
+    int32_t *cnt_out;        /* device int32 [ny][nx], nullable */
+    int32_t *nn_idx_out;     /* device int32 [ny][nx], nullable */
+    float *nn_z_out;         /* device float [ny][nx], nullable */
+} auv_batch_item;
+
+typedef struct auv_batch auv_batch;
+
+/* Validate `count` items (host array, copied) and plan the batch.  tune_path
+ * (nullable) names a table written by auv_batch_autotune; items of a class it
+ * does not list get the defaults (bin = smallest power of two >= radius,
+ * kernel form chosen as by AUV_ALGO_AUTO).  Errors: AUV_ERR_INVALID for a bad
+ * item (its index is in the message). */
+auv_status auv_batch_plan(const auv_batch_item *items, int32_t count,
+                          const char *tune_path, auv_batch **out);
+
+/* Device workspace (bytes) that auv_batch_launch and auv_batch_launch_plain
+ * need for this batch. */
+auv_status auv_batch_workspace_size(const auv_batch *batch, size_t *bytes);
+
+/* Run the batch.  The first call with a given workspace uploads the item
+ * tables into it, captures the work into a HIP graph and launches it; later
+ * calls with the same workspace replay the graph.  The inputs and outputs of
+ * the items must stay at the same addresses between calls.  Asynchronous on
+ * `stream` (which must not be in capture). */
+auv_status auv_batch_launch(auv_batch *batch, void *ws, size_t ws_bytes,
+                            auv_stream stream);
+
+/* The plain form of the same batch, for comparison: for each item in turn,
+ * auv_bin_points with the default bin size and auv_interp_idw with
+ * AUV_ALGO_AUTO, launched one after another on `stream` (no graph). */
+auv_status auv_batch_launch_plain(auv_batch *batch, void *ws, size_t ws_bytes,
+                                  auv_stream stream);
+
+/* Autotuner: group the items into classes (expected soundings per disk and
+ * grid side, both bucketed by powers of two), time the candidate (bin size,
+ * kernel form) pairs on one representative item per class, and write the
+ * fastest per class to tune_path (a small text table).  Synchronises
+ * `stream`; uses `ws` (at least auv_batch_workspace_size of a batch planned
+ * from the same items) as scratch, and overwrites the items' outputs. */
+auv_status auv_batch_autotune(const auv_batch_item *items, int32_t count, void *ws,
+                              size_t ws_bytes, auv_stream stream, const char *tune_path);
+
+/* Per-item plan actually used (for reports): bin_log2 and kernel form. */
+auv_status auv_batch_item_plan(const auv_batch *batch, int32_t item, int32_t *bin_log2,
+                               int32_t *algo);
+
+void auv_batch_destroy(auv_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

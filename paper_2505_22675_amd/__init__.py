@@ -51,6 +51,15 @@ class auv_idw_params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("algo", ctypes.c_int32)]
 
 
+class auv_batch_item(ctypes.Structure):
+    _fields_ = [("grid", auv_grid_desc),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("n", ctypes.c_int64),
+                ("params", auv_idw_params),
+                ("z_out", ctypes.c_void_p), ("cnt_out", ctypes.c_void_p),
+                ("nn_idx_out", ctypes.c_void_p), ("nn_z_out", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -81,6 +90,14 @@ def load_library(path: str = LIB_PATH):
         "auv_interp_nearest": ([vp, vp, d, vp, vp, vp], ctypes.c_int),
         "auv_resample_bilinear": ([vp, P(auv_grid_desc), vp, P(auv_grid_desc), vp],
                                   ctypes.c_int),
+        "auv_batch_plan": ([P(auv_batch_item), i32, ctypes.c_char_p, P(vp)], ctypes.c_int),
+        "auv_batch_workspace_size": ([vp, P(ctypes.c_size_t)], ctypes.c_int),
+        "auv_batch_launch": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
+        "auv_batch_launch_plain": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
+        "auv_batch_autotune": ([P(auv_batch_item), i32, vp, ctypes.c_size_t, vp,
+                                ctypes.c_char_p], ctypes.c_int),
+        "auv_batch_item_plan": ([vp, i32, P(i32), P(i32)], ctypes.c_int),
+        "auv_batch_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -294,3 +311,87 @@ def grid_idw(grid: Grid, bins: Bins, power=2.0, radius=None, min_pts=1, max_pts=
     auv_interp_idw(grid, bins, p, out["z"], out.get("cnt"), out.get("nn_idx"),
                    out.get("nn_z"), stream)
     return out
+
+
+# ------------------------------------------------------------------ batches
+
+
+def batch_item(desc: auv_grid_desc, x, y, z, params: auv_idw_params, z_out, cnt_out=None,
+               nn_idx_out=None, nn_z_out=None) -> auv_batch_item:
+    """Fill an ``auv_batch_item`` from device tensors (which the caller keeps alive
+    and in place for as long as the batch is launched)."""
+    n = int(x.numel())
+    cells = desc.nx * desc.ny
+    it = auv_batch_item()
+    it.grid = desc
+    it.x = _dev(x, torch.float64, "x", n)
+    it.y = _dev(y, torch.float64, "y", n)
+    it.z = _dev(z, torch.float64, "z", n)
+    it.n = n
+    it.params = params
+    it.z_out = _dev(z_out, torch.float32, "z_out", cells)
+    it.cnt_out = _dev(cnt_out, torch.int32, "cnt_out", cells)
+    it.nn_idx_out = _dev(nn_idx_out, torch.int32, "nn_idx_out", cells)
+    it.nn_z_out = _dev(nn_z_out, torch.float32, "nn_z_out", cells)
+    return it
+
+
+def _items_array(items):
+    arr = (auv_batch_item * len(items))()
+    for i, it in enumerate(items):
+        arr[i] = it
+    return arr
+
+
+class Batch:
+    """Owning wrapper of an ``auv_batch*`` plus its device workspace."""
+
+    def __init__(self, items, tune_path: str | None = None, device=None):
+        lib = load_library()
+        self.items = list(items)
+        arr = _items_array(self.items)
+        h = ctypes.c_void_p()
+        path = tune_path.encode() if tune_path else None
+        _check(lib.auv_batch_plan(arr, len(self.items), path, ctypes.byref(h)))
+        self._h = h
+        nbytes = ctypes.c_size_t()
+        _check(lib.auv_batch_workspace_size(h, ctypes.byref(nbytes)))
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        # 256-byte aligned (the caching allocator hands out 512-byte aligned blocks)
+        self.ws = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=dev)
+        self.ws_bytes = int(nbytes.value)
+
+    def launch(self, stream=None):
+        """auv_batch_launch: capture on first use, replay afterwards."""
+        _check(_lib.auv_batch_launch(self._h, ctypes.c_void_p(self.ws.data_ptr()),
+                                     self.ws_bytes, _stream(stream)))
+
+    def launch_plain(self, stream=None):
+        """auv_batch_launch_plain: item after item, default sizes, no graph."""
+        _check(_lib.auv_batch_launch_plain(self._h, ctypes.c_void_p(self.ws.data_ptr()),
+                                           self.ws_bytes, _stream(stream)))
+
+    def item_plan(self, i: int):
+        """(bin_log2, algo) the batched form uses for item i."""
+        s, a = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.auv_batch_item_plan(self._h, i, ctypes.byref(s), ctypes.byref(a)))
+        return s.value, a.value
+
+    def close(self):
+        if self._h:
+            _lib.auv_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def auv_batch_autotune(items, ws: torch.Tensor, tune_path: str, stream=None):
+    """Time (bin size, kernel form) candidates per item class; write tune_path."""
+    lib = load_library()
+    arr = _items_array(items)
+    _check(lib.auv_batch_autotune(arr, len(items), _dev(ws, torch.uint8, "ws"), ws.numel(),
+                                  _stream(stream), tune_path.encode()))

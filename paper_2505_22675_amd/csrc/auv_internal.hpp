@@ -22,6 +22,13 @@ constexpr float kResidualUnit = 1.0f / 32768.0f;
 auv_status fail(auv_status st, const std::string &msg);
 auv_status hip_fail(hipError_t e, const char *what);
 
+#define AUV_TRY_S(expr)                                                        \
+    do {                                                                       \
+        auv_status s_ = (expr);                                                \
+        if (s_ != AUV_OK)                                                      \
+            return s_;                                                         \
+    } while (0)
+
 #define AUV_HIP(call)                                                          \
     do {                                                                       \
         hipError_t e_ = (call);                                                \
@@ -102,6 +109,37 @@ struct BinWorkspace {
 size_t bin_workspace_layout(int64_t n, const BinGeom &g, char *base,
                             BinWorkspace *w);
 
+// Binned structure-of-arrays outputs.
+struct SoA {
+    int32_t *X, *Y;
+    uint32_t *res;
+    float *z;
+    int32_t *idx;
+};
+
+// Everything one item needs for the row-wise counting sort.
+struct RowItem {
+    const double *x, *y, *z;
+    int64_t n;
+    double x0, y0, lo, hix, hiy;
+    int32_t s, hB, nbx, nby;
+    int32_t nblk;  // k_row_hist blocks of this item (drop partials)
+    int32_t *row_count, *row_start, *rowid, *pos, *colkey, *drops, *cell_start;
+    int4 *rec;
+    unsigned long long *keys, *keys2, *stats;
+    SoA o;
+};
+
+bool row_path_ok(const BinGeom &geom);
+RowItem make_row_item(const auv_grid *g, const BinGeom &geom, const double *x,
+                      const double *y, const double *z, int64_t n, const BinWorkspace &w);
+int32_t row_hist_blocks(int64_t n);
+int32_t row_scatter_blocks(int64_t n);
+auv_status launch_binning_batch(const RowItem *d_items, const int32_t *d_hist_off,
+                                const int32_t *d_scatter_off, const int32_t *d_sort_off,
+                                int32_t count, int32_t hist_blocks, int32_t scatter_blocks,
+                                int32_t sort_blocks, hipStream_t st);
+
 auv_status launch_binning(const auv_grid *g, const BinGeom &geom,
                           const double *x, const double *y, const double *z,
                           int64_t n, const BinWorkspace &w, hipStream_t st);
@@ -121,6 +159,7 @@ struct IdwArgs {
     float r2f;                // radius^2 in m^2, FP32 (precision variants)
     double x0, y0;            // grid origin (precision variants)
     bool dense;               // use the dense (ring search, top-k) form
+    int32_t pmode;            // 1, 2, 3: integer power (fast weights), 0: general
     float *z_out;
     int32_t *cnt_out;
     int32_t *nn_idx_out;

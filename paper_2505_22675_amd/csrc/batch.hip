@@ -1,0 +1,778 @@
+// Batches of independent, uneven gridding problems.
+//
+//   auv_batch_plan      host: validate items, pick bin size and kernel form per
+//                       item (autotune table or defaults), lay out a workspace
+//   auv_batch_launch    first call: upload item tables, capture
+//                         batched binning (5 launches for all items)
+//                         -> queue reset -> one persistent IDW launch per
+//                         kernel form (sparse window / dense top-k, on two
+//                         concurrent branches), + per-item launches for items
+//                         they do not cover
+//                       into a HIP graph; later calls replay the graph
+//   auv_batch_launch_plain  the same items one after another, default sizes
+//   auv_batch_autotune  time (bin size, form) candidates per item class
+//
+// The persistent kernels: each 64-lane wave takes its home queue (one per XCD:
+// blocks are dealt round-robin to the 8 XCDs, so block b runs on XCD b % 8),
+// pulls (item, tile) work with one atomic per tile, and moves on to the other
+// queues when its own is drained.  Items are assigned to queues by longest
+// processing time first on an estimated cost, so each XCD's L2 mostly sees
+// the bins of a few items.
+#include "idw_dense_impl.hpp"
+#include "idw_window_impl.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+namespace auv {
+
+namespace {
+
+constexpr int kQueues = 8;
+constexpr int kBatchDenseK = 16;  // largest max_pts the persistent dense path keeps
+
+struct IdwItem {
+    auv_bin_view bv;
+    IdwArgs a;
+    WinGeom g;
+    int32_t ntx, ntiles;
+    int32_t dense, pmode;
+};
+
+__global__ void k_reset_queues(int32_t *qhead)
+{
+    if (threadIdx.x < 2 * kQueues)
+        qhead[threadIdx.x] = 0;
+}
+
+template <int kPmode, int kChunks>
+__device__ inline void run_window(const IdwItem &it, int tile, const win::WinSmem &sm)
+{
+    win::window_tile<3, kPmode, true, kChunks, AUV_P_FP32_REBASE>(it.bv, it.a, it.g, tile,
+                                                                  it.ntx, sm);
+}
+
+// Pull the next (item, tile) from queue q; -1 when the queue is drained.  One
+// atomic per tile, issued by lane 0 and broadcast (wave-uniform result).
+__device__ inline int pull(int32_t *qhead, int q, int len)
+{
+    int t = 0;
+    if (threadIdx.x == 0)
+        t = atomicAdd(&qhead[q], 1);
+    t = __builtin_amdgcn_readfirstlane(t);
+    return t < len ? t : -1;
+}
+
+// Persistent kernels, one per kernel form (the forms' register budgets differ
+// by 2x, so sharing one kernel would halve the occupancy of the sparse form).
+// Each wave starts on the queue of its own XCD and then drains the others.
+__global__ __launch_bounds__(64) void k_idw_batch_window(const IdwItem *__restrict__ items,
+                                                         const int2 *__restrict__ work,
+                                                         const int32_t *__restrict__ qoff,
+                                                         int32_t *__restrict__ qhead)
+{
+    __shared__ float2 s_nd[win::kAcc];
+    __shared__ int s_cnt[win::kAcc];
+    __shared__ unsigned long long s_key[win::kAcc];
+    __shared__ float s_emax[win::kAcc];
+    __shared__ int s_beg[win::kMaxRows];
+    __shared__ int s_off[win::kMaxRows + 1];
+    const win::WinSmem sm{s_nd, s_cnt, s_key, nullptr, nullptr, nullptr, s_emax, s_beg, s_off};
+    const int home = blockIdx.x & (kQueues - 1);
+    for (int k = 0; k < kQueues; ++k) {
+        const int q = (home + k) & (kQueues - 1);
+        const int len = qoff[q + 1] - qoff[q];
+        for (int t = pull(qhead, q, len); t >= 0; t = pull(qhead, q, len)) {
+            // wave-uniform work entry: the item descriptor is then read with
+            // scalar loads into SGPRs instead of occupying vector registers
+            const int2 wv = work[qoff[q] + t];
+            const int2 w = make_int2(__builtin_amdgcn_readfirstlane(wv.x),
+                                     __builtin_amdgcn_readfirstlane(wv.y));
+            const IdwItem &it = items[w.x];
+            // integer powers share one variant (the power is a runtime
+            // value there); a general power needs the rescaling variant
+            if (it.pmode != 0)
+                run_window<-1, 1>(it, w.y, sm);
+            else
+                run_window<0, 1>(it, w.y, sm);
+        }
+    }
+}
+
+__global__ __launch_bounds__(64) void k_idw_batch_dense(const IdwItem *__restrict__ items,
+                                                        const int2 *__restrict__ work,
+                                                        const int32_t *__restrict__ qoff,
+                                                        int32_t *__restrict__ qhead)
+{
+    const int home = blockIdx.x & (kQueues - 1);
+    for (int k = 0; k < kQueues; ++k) {
+        const int q = (home + k) & (kQueues - 1);
+        const int len = qoff[q + 1] - qoff[q];
+        for (int t = pull(qhead, q, len); t >= 0; t = pull(qhead, q, len)) {
+            // wave-uniform work entry: the item descriptor is then read with
+            // scalar loads into SGPRs instead of occupying vector registers
+            const int2 wv = work[qoff[q] + t];
+            const int2 w = make_int2(__builtin_amdgcn_readfirstlane(wv.x),
+                                     __builtin_amdgcn_readfirstlane(wv.y));
+            const IdwItem &it = items[w.x];
+            dense::dense_tile<3, kBatchDenseK>(it.bv, it.a, w.y, it.ntx, it.pmode);
+        }
+    }
+}
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int pmode_of(double p)
+{
+    if (p == 1.0)
+        return 1;
+    if (p == 2.0)
+        return 2;
+    if (p == 3.0)
+        return 3;
+    return 0;
+}
+
+// Expected soundings per disk: input count over the grid grown by r.
+double disk_population(const auv_batch_item &it)
+{
+    const double r = it.params.radius;
+    const double area = (it.grid.nx * it.grid.dx + 2 * r) * (it.grid.ny * it.grid.dy + 2 * r);
+    return (double)it.n / area * 3.141592653589793 * r * r;
+}
+
+struct ClassKey {
+    int dens, side;
+    bool operator<(const ClassKey &o) const
+    {
+        return dens != o.dens ? dens < o.dens : side < o.side;
+    }
+};
+
+ClassKey class_of(const auv_batch_item &it)
+{
+    ClassKey k;
+    k.dens = (int)std::floor(std::log2(disk_population(it) + 1.0));
+    k.side = (int)std::lround(std::log2((double)std::max(it.grid.nx, it.grid.ny)));
+    return k;
+}
+
+bool dense_allowed(const auv_batch_item &it)
+{
+    return it.params.max_pts >= 1 && it.params.max_pts <= 32 &&
+           it.params.precision == AUV_P_FP32_REBASE;
+}
+
+struct Choice {
+    int32_t bin_log2;
+    int32_t algo;  // AUV_ALGO_SPARSE or AUV_ALGO_DENSE
+};
+
+// Candidate (bin size, form) pairs the autotuner may time for an item.
+std::vector<Choice> candidates(const auv_batch_item &it, int32_t sR)
+{
+    std::vector<Choice> c;
+    for (int d = -1; d <= 1; ++d)
+        if (sR + d >= 12 && sR + d <= 26)
+            c.push_back({sR + d, AUV_ALGO_SPARSE});
+    if (dense_allowed(it) && disk_population(it) >= 0.5 * it.params.max_pts)
+        for (int d = -4; d <= -1; ++d)
+            if (sR + d >= 12)
+                c.push_back({sR + d, AUV_ALGO_DENSE});
+    return c;
+}
+
+}  // namespace
+
+}  // namespace auv
+
+// ------------------------------------------------------------- the batch --
+
+struct auv_batch {
+    std::vector<auv_batch_item> items;
+    std::vector<auv_grid> grids;
+    std::vector<auv::BinGeom> geom;        // batched form
+    std::vector<auv::BinGeom> geom_plain;  // plain form
+    std::vector<int32_t> algo;             // batched form
+    std::vector<size_t> slice_off;         // per-item workspace slice
+    std::vector<size_t> slice_size;
+    std::vector<uint8_t> persistent;       // covered by the persistent kernel
+    size_t tables_bytes = 0, ws_bytes = 0;
+    // host copies of the device tables (valid for `bound_ws`)
+    std::vector<auv::RowItem> rows;
+    std::vector<auv::IdwItem> idw;
+    std::vector<int32_t> offs;  // hist, scatter, sort offsets, then qoff
+    std::vector<int2> work;
+    int32_t hist_blocks = 0, scatter_blocks = 0, sort_blocks = 0, nrow_items = 0;
+    int32_t nwork_window = 0, nwork_dense = 0;
+    hipStream_t cap_stream2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    std::vector<int32_t> row_items;  // items binned by the batched row path
+    // graph
+    void *bound_ws = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace auv {
+
+namespace {
+
+auv_status validate_item(const auv_batch_item &it, int i)
+{
+    const std::string tag = "item " + std::to_string(i) + ": ";
+    if (it.n < 0 || it.n >= INT32_MAX)
+        return fail(AUV_ERR_INVALID, tag + "n must be in [0, 2^31-1)");
+    if (it.n > 0 && (!it.x || !it.y || !it.z))
+        return fail(AUV_ERR_INVALID, tag + "null sounding pointer");
+    if (!it.z_out)
+        return fail(AUV_ERR_INVALID, tag + "z_out is null");
+    const auv_idw_params &p = it.params;
+    if (!(p.power > 0.0) || !(p.power <= 64.0) || p.min_pts < 0 || p.max_pts < 0)
+        return fail(AUV_ERR_INVALID, tag + "bad power / min_pts / max_pts");
+    if (p.precision != AUV_P_FP32_REBASE)
+        return fail(AUV_ERR_INVALID, tag + "batches run the exact FP64-rebase form only");
+    if (p.algo < AUV_ALGO_AUTO || p.algo > AUV_ALGO_DENSE)
+        return fail(AUV_ERR_INVALID, tag + "unknown algo");
+    return AUV_OK;
+}
+
+// Build the bin view and IDW arguments of item i with its workspace slice.
+void item_views(const auv_batch *b, int i, char *ws, const BinGeom &geom, int32_t algo,
+                BinWorkspace *w, auv_bin_view *bv, IdwArgs *a)
+{
+    const auv_batch_item &it = b->items[i];
+    bin_workspace_layout(it.n, geom, ws + b->slice_off[i], w);
+    auv_bin_view v{};
+    v.cell_start = w->cell_start;
+    v.X = w->X;
+    v.Y = w->Y;
+    v.res = w->res;
+    v.z = w->z;
+    v.idx = w->idx;
+    v.rec = w->rec;
+    v.nbx = geom.nbx;
+    v.nby = geom.nby;
+    v.halo = geom.halo;
+    v.bin_log2 = geom.s;
+    v.R = geom.R;
+    int bits = 1;
+    while (bits < 31 && (int64_t(1) << bits) < it.n)
+        ++bits;
+    v.idx_bits = bits;
+    *bv = v;
+    IdwArgs x;
+    std::memset(&x, 0, sizeof(x));
+    x.dx = it.grid.dx;
+    x.dy = it.grid.dy;
+    x.nx = it.grid.nx;
+    x.ny = it.grid.ny;
+    x.R = geom.R;
+    x.R_stage = geom.R;
+    x.inv_r2 = (float)(1.0 / ((double)geom.R * geom.R));
+    x.r2f = (float)(it.params.radius * it.params.radius);
+    x.x0 = it.grid.x0;
+    x.y0 = it.grid.y0;
+    x.power = (float)it.params.power;
+    x.min_pts = it.params.min_pts;
+    x.max_pts = it.params.max_pts;
+    x.precision = AUV_P_FP32_REBASE;
+    x.mode = (it.nn_idx_out || it.nn_z_out) ? 3 : 1;
+    x.z_out = it.z_out;
+    x.cnt_out = it.cnt_out;
+    x.nn_idx_out = it.nn_idx_out;
+    x.nn_z_out = it.nn_z_out;
+    x.dense = algo == AUV_ALGO_DENSE;
+    x.pmode = pmode_of(it.params.power);
+    *a = x;
+}
+
+int32_t auto_algo(const auv_batch_item &it)
+{
+    if (it.params.algo != AUV_ALGO_AUTO)
+        return it.params.algo;
+    return dense_allowed(it) && disk_population(it) >= it.params.max_pts ? AUV_ALGO_DENSE
+                                                                          : AUV_ALGO_SPARSE;
+}
+
+std::map<ClassKey, Choice> read_tune(const char *path)
+{
+    std::map<ClassKey, Choice> t;
+    if (!path)
+        return t;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string tag, k1, k2;
+        ClassKey key;
+        Choice c;
+        double ms;
+        if (is >> tag >> key.dens >> key.side >> k1 >> c.bin_log2 >> k2 >> c.algo && tag == "class")
+            t[key] = c;
+        (void)ms;
+    }
+    return t;
+}
+
+// Build the device tables for workspace `ws` (host copies kept in the batch).
+auv_status build_tables(auv_batch *b, char *ws)
+{
+    const int count = (int)b->items.size();
+    b->rows.assign(count, RowItem{});
+    b->idw.assign(count, IdwItem{});
+    b->row_items.clear();
+    std::vector<int32_t> hist(1, 0), scat(1, 0), sort(1, 0);
+    std::vector<double> cost(count, 0.0);
+    for (int i = 0; i < count; ++i) {
+        const auv_batch_item &it = b->items[i];
+        BinWorkspace w;
+        auv_bin_view bv;
+        IdwArgs a;
+        item_views(b, i, ws, b->geom[i], b->algo[i], &w, &bv, &a);
+        if (row_path_ok(b->geom[i])) {
+            b->rows[b->row_items.size()] =
+                make_row_item(&b->grids[i], b->geom[i], it.x, it.y, it.z, it.n, w);
+            b->row_items.push_back(i);
+            hist.push_back(hist.back() + row_hist_blocks(it.n));
+            scat.push_back(scat.back() + row_scatter_blocks(it.n));
+            sort.push_back(sort.back() + b->geom[i].nby);
+        }
+        IdwItem &d = b->idw[i];
+        d.bv = bv;
+        d.a = a;
+        d.pmode = pmode_of(it.params.power);
+        d.dense = b->algo[i] == AUV_ALGO_DENSE;
+        bool ok = true;
+        if (d.dense) {
+            ok = it.params.max_pts >= 1 && it.params.max_pts <= kBatchDenseK;
+            d.ntx = (it.grid.nx + 7) / 8;
+            d.ntiles = d.ntx * ((it.grid.ny + 7) / 8);
+        } else {
+            ok = window_geometry(a, &d.g) && d.g.nchunks == 1;
+            const unsigned __int128 top = (unsigned __int128)((unsigned long long)a.R * a.R)
+                                          << bv.idx_bits;
+            ok = ok && top < ((unsigned __int128)1 << 64);
+            d.ntx = (it.grid.nx + win::kTN - 1) / win::kTN;
+            d.ntiles = d.ntx * ((it.grid.ny + win::kTN - 1) / win::kTN);
+        }
+        ok = ok && row_path_ok(b->geom[i]);
+        b->persistent[i] = ok ? 1 : 0;
+        cost[i] = (double)it.n + (double)it.grid.nx * it.grid.ny * (d.dense ? 4.0 : 1.0);
+    }
+    b->nrow_items = (int32_t)b->row_items.size();
+    b->hist_blocks = hist.back();
+    b->scatter_blocks = scat.back();
+    b->sort_blocks = sort.back();
+    // longest processing time first: items to the least loaded queue, one
+    // queue set per kernel form
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i)
+        order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    b->work.clear();
+    std::vector<int32_t> qoff(2 * kQueues + 1, 0);
+    for (int form = 0; form < 2; ++form) {
+        std::vector<std::vector<int>> q(kQueues);
+        std::vector<double> load(kQueues, 0.0);
+        for (int i : order) {
+            if (!b->persistent[i] || b->idw[i].dense != form)
+                continue;
+            const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            q[k].push_back(i);
+            load[k] += cost[i];
+        }
+        for (int k = 0; k < kQueues; ++k) {
+            for (int i : q[k])
+                for (int t = 0; t < b->idw[i].ntiles; ++t)
+                    b->work.push_back(make_int2(i, t));
+            qoff[form * kQueues + k + 1] = (int32_t)b->work.size();
+        }
+    }
+    b->nwork_window = qoff[kQueues];
+    b->nwork_dense = qoff[2 * kQueues] - qoff[kQueues];
+    b->offs.clear();
+    b->offs.insert(b->offs.end(), hist.begin(), hist.end());
+    b->offs.insert(b->offs.end(), scat.begin(), scat.end());
+    b->offs.insert(b->offs.end(), sort.begin(), sort.end());
+    b->offs.insert(b->offs.end(), qoff.begin(), qoff.end());
+    return AUV_OK;
+}
+
+// Table region at the start of the workspace.
+struct Tables {
+    RowItem *rows;
+    IdwItem *idw;
+    int32_t *offs;
+    int32_t *qhead;
+    int2 *work;
+};
+
+Tables table_ptrs(const auv_batch *b, char *ws)
+{
+    const size_t count = b->items.size();
+    size_t off = 0;
+    Tables t;
+    t.rows = reinterpret_cast<RowItem *>(ws + off);
+    off += align256(sizeof(RowItem) * count);
+    t.idw = reinterpret_cast<IdwItem *>(ws + off);
+    off += align256(sizeof(IdwItem) * count);
+    t.offs = reinterpret_cast<int32_t *>(ws + off);
+    off += align256(sizeof(int32_t) * (3 * (count + 1) + 2 * kQueues + 1));
+    t.qhead = reinterpret_cast<int32_t *>(ws + off);
+    off += align256(sizeof(int32_t) * 2 * kQueues);
+    t.work = reinterpret_cast<int2 *>(ws + off);
+    return t;
+}
+
+size_t tables_size(size_t count, size_t max_tiles)
+{
+    return align256(sizeof(RowItem) * count) + align256(sizeof(IdwItem) * count) +
+           align256(sizeof(int32_t) * (3 * (count + 1) + 2 * kQueues + 1)) +
+           align256(sizeof(int32_t) * 2 * kQueues) +
+           align256(sizeof(int2) * std::max<size_t>(max_tiles, 1));
+}
+
+// Enqueue the whole batched form on `st` (captured by the caller).
+auv_status enqueue_batched(auv_batch *b, char *ws, hipStream_t st)
+{
+    const Tables t = table_ptrs(b, ws);
+    const int count = (int)b->items.size();
+    const int nr = b->nrow_items;
+    AUV_TRY_S(launch_binning_batch(t.rows, t.offs, t.offs + (nr + 1), t.offs + 2 * (nr + 1), nr,
+                                   b->hist_blocks, b->scatter_blocks, b->sort_blocks, st));
+    for (int i = 0; i < count; ++i) {
+        if (row_path_ok(b->geom[i]))
+            continue;
+        BinWorkspace w;
+        auv_bin_view bv;
+        IdwArgs a;
+        item_views(b, i, ws, b->geom[i], b->algo[i], &w, &bv, &a);
+        const auv_batch_item &it = b->items[i];
+        AUV_TRY_S(launch_binning(&b->grids[i], b->geom[i], it.x, it.y, it.z, it.n, w, st));
+    }
+    if (!b->work.empty()) {
+        k_reset_queues<<<1, 64, 0, st>>>(t.qhead);
+        int dev = 0, cus = 256;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        const int32_t *qoff = t.offs + 3 * (nr + 1);
+        // the dense form runs on a forked branch of the graph, concurrently
+        if (b->nwork_dense > 0) {
+            AUV_HIP(hipEventRecord(b->ev_fork, st));
+            AUV_HIP(hipStreamWaitEvent(b->cap_stream2, b->ev_fork, 0));
+            k_idw_batch_dense<<<std::min<int>(b->nwork_dense, cus * 8), 64, 0, b->cap_stream2>>>(
+                t.idw, t.work, qoff + kQueues, t.qhead + kQueues);
+            AUV_HIP(hipGetLastError());
+            AUV_HIP(hipEventRecord(b->ev_join, b->cap_stream2));
+        }
+        if (b->nwork_window > 0)
+            k_idw_batch_window<<<std::min<int>(b->nwork_window, cus * 16), 64, 0, st>>>(
+                t.idw, t.work, qoff, t.qhead);
+        AUV_HIP(hipGetLastError());
+        if (b->nwork_dense > 0)
+            AUV_HIP(hipStreamWaitEvent(st, b->ev_join, 0));
+    }
+    for (int i = 0; i < count; ++i) {
+        if (b->persistent[i])
+            continue;
+        AUV_TRY_S(launch_idw(b->idw[i].bv, b->idw[i].a, st));
+    }
+    return AUV_OK;
+}
+
+}  // namespace
+}  // namespace auv
+
+using namespace auv;
+
+extern "C" {
+
+auv_status auv_batch_plan(const auv_batch_item *items, int32_t count, const char *tune_path,
+                          auv_batch **out)
+{
+    if (!out)
+        return fail(AUV_ERR_INVALID, "out is null");
+    *out = nullptr;
+    if (!items || count < 1)
+        return fail(AUV_ERR_INVALID, "need at least one item");
+    auv_batch *b = new (std::nothrow) auv_batch;
+    if (!b)
+        return fail(AUV_ERR_INVALID, "out of host memory");
+    b->items.assign(items, items + count);
+    b->grids.resize(count);
+    b->geom.resize(count);
+    b->geom_plain.resize(count);
+    b->algo.resize(count);
+    b->slice_off.resize(count);
+    b->slice_size.resize(count);
+    b->persistent.assign(count, 0);
+    const std::map<ClassKey, Choice> tune = read_tune(tune_path);
+    size_t off = 0, max_tiles = 0;
+    for (int i = 0; i < count; ++i) {
+        const auv_batch_item &it = b->items[i];
+        auv_status st = validate_item(it, i);
+        if (st == AUV_OK) {
+            auv_grid *g = nullptr;
+            st = auv_grid_create(&it.grid, &g);
+            if (st == AUV_OK) {
+                b->grids[i] = *g;
+                auv_grid_destroy(g);
+            }
+        }
+        if (st == AUV_OK)
+            st = bin_geometry(&b->grids[i], it.params.radius, 0, &b->geom_plain[i]);
+        if (st != AUV_OK) {
+            delete b;
+            return st;
+        }
+        Choice c{b->geom_plain[i].s, auto_algo(it)};
+        const auto f = tune.find(class_of(it));
+        if (f != tune.end() && it.params.algo == AUV_ALGO_AUTO &&
+            (f->second.algo == AUV_ALGO_SPARSE || dense_allowed(it)))
+            c = f->second;
+        b->algo[i] = c.algo;
+        st = bin_geometry(&b->grids[i], it.params.radius, c.bin_log2, &b->geom[i]);
+        if (st != AUV_OK) {
+            b->geom[i] = b->geom_plain[i];
+            b->algo[i] = auto_algo(it);
+        }
+        // slice: the largest layout any form or autotune candidate may use
+        size_t need = std::max(bin_workspace_layout(it.n, b->geom[i], nullptr, nullptr),
+                               bin_workspace_layout(it.n, b->geom_plain[i], nullptr, nullptr));
+        for (const Choice &cc : candidates(it, b->geom_plain[i].s)) {
+            BinGeom gg;
+            if (bin_geometry(&b->grids[i], it.params.radius, cc.bin_log2, &gg) == AUV_OK &&
+                (int64_t)gg.nbx * gg.nby <= (int64_t)1 << 24)
+                need = std::max(need, bin_workspace_layout(it.n, gg, nullptr, nullptr));
+        }
+        b->slice_size[i] = align256(need);
+        const size_t tiles8 = (size_t)((it.grid.nx + 7) / 8) * ((it.grid.ny + 7) / 8);
+        max_tiles += tiles8;
+    }
+    b->tables_bytes = align256(tables_size(count, max_tiles));
+    off = b->tables_bytes;
+    for (int i = 0; i < count; ++i) {
+        b->slice_off[i] = off;
+        off += b->slice_size[i];
+    }
+    b->ws_bytes = off;
+    *out = b;
+    return AUV_OK;
+}
+
+auv_status auv_batch_workspace_size(const auv_batch *batch, size_t *bytes)
+{
+    if (!batch || !bytes)
+        return fail(AUV_ERR_INVALID, "null argument");
+    *bytes = batch->ws_bytes;
+    return AUV_OK;
+}
+
+auv_status auv_batch_item_plan(const auv_batch *batch, int32_t item, int32_t *bin_log2,
+                               int32_t *algo)
+{
+    if (!batch || item < 0 || item >= (int32_t)batch->items.size())
+        return fail(AUV_ERR_INVALID, "bad batch or item");
+    if (bin_log2)
+        *bin_log2 = batch->geom[item].s;
+    if (algo)
+        *algo = batch->algo[item];
+    return AUV_OK;
+}
+
+static auv_status check_ws(const auv_batch *b, void *ws, size_t ws_bytes)
+{
+    if (!b)
+        return fail(AUV_ERR_INVALID, "batch is null");
+    if (!ws || ws_bytes < b->ws_bytes)
+        return fail(AUV_ERR_BUDGET, "workspace smaller than auv_batch_workspace_size");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+        return fail(AUV_ERR_INVALID, "workspace must be 256-byte aligned");
+    return AUV_OK;
+}
+
+auv_status auv_batch_launch(auv_batch *b, void *ws, size_t ws_bytes, auv_stream stream)
+{
+    AUV_TRY_S(check_ws(b, ws, ws_bytes));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(ws);
+    if (b->exec && b->bound_ws == ws) {
+        AUV_HIP(hipGraphLaunch(b->exec, st));
+        return AUV_OK;
+    }
+    // (re)bind: tables for this workspace, then capture
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    AUV_TRY_S(build_tables(b, base));
+    const Tables t = table_ptrs(b, base);
+    AUV_HIP(hipMemcpyAsync(t.rows, b->rows.data(), sizeof(RowItem) * b->rows.size(),
+                           hipMemcpyHostToDevice, st));
+    AUV_HIP(hipMemcpyAsync(t.idw, b->idw.data(), sizeof(IdwItem) * b->idw.size(),
+                           hipMemcpyHostToDevice, st));
+    AUV_HIP(hipMemcpyAsync(t.offs, b->offs.data(), sizeof(int32_t) * b->offs.size(),
+                           hipMemcpyHostToDevice, st));
+    if (!b->work.empty())
+        AUV_HIP(hipMemcpyAsync(t.work, b->work.data(), sizeof(int2) * b->work.size(),
+                               hipMemcpyHostToDevice, st));
+    // the tables must be in place before any replay reads them
+    AUV_HIP(hipStreamSynchronize(st));
+    if (!b->cap_stream) {
+        AUV_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+        AUV_HIP(hipStreamCreateWithFlags(&b->cap_stream2, hipStreamNonBlocking));
+        AUV_HIP(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+        AUV_HIP(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
+    }
+    AUV_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    const auv_status es = enqueue_batched(b, base, b->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(b->cap_stream, &g);
+    if (es != AUV_OK) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return es;
+    }
+    if (ce != hipSuccess)
+        return hip_fail(ce, "hipStreamEndCapture");
+    b->graph = g;
+    AUV_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->bound_ws = ws;
+    AUV_HIP(hipGraphLaunch(b->exec, st));
+    return AUV_OK;
+}
+
+auv_status auv_batch_launch_plain(auv_batch *b, void *ws, size_t ws_bytes, auv_stream stream)
+{
+    AUV_TRY_S(check_ws(b, ws, ws_bytes));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(ws);
+    for (int i = 0; i < (int)b->items.size(); ++i) {
+        const auv_batch_item &it = b->items[i];
+        BinWorkspace w;
+        auv_bin_view bv;
+        IdwArgs a;
+        item_views(b, i, base, b->geom_plain[i], auto_algo(it), &w, &bv, &a);
+        AUV_TRY_S(launch_binning(&b->grids[i], b->geom_plain[i], it.x, it.y, it.z, it.n, w, st));
+        AUV_TRY_S(launch_idw(bv, a, st));
+    }
+    return AUV_OK;
+}
+
+auv_status auv_batch_autotune(const auv_batch_item *items, int32_t count, void *ws,
+                              size_t ws_bytes, auv_stream stream, const char *tune_path)
+{
+    if (!tune_path)
+        return fail(AUV_ERR_INVALID, "tune_path is null");
+    auv_batch *b = nullptr;
+    AUV_TRY_S(auv_batch_plan(items, count, nullptr, &b));
+    struct Guard {
+        auv_batch *b;
+        ~Guard() { auv_batch_destroy(b); }
+    } guard{b};
+    AUV_TRY_S(check_ws(b, ws, ws_bytes));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(ws);
+    // one representative per class: the item with the most soundings
+    std::map<ClassKey, int> rep;
+    for (int i = 0; i < count; ++i) {
+        const ClassKey k = class_of(b->items[i]);
+        const auto f = rep.find(k);
+        if (f == rep.end() || b->items[i].n > b->items[f->second].n)
+            rep[k] = i;
+    }
+    hipEvent_t e0, e1;
+    AUV_HIP(hipEventCreate(&e0));
+    AUV_HIP(hipEventCreate(&e1));
+    std::ostringstream table;
+    table << "# auvgrid autotune table: class <log2 disk population> <log2 grid side> "
+             "bin_log2 <s> algo <1 sparse | 2 dense> ms <time>\n";
+    auv_status result = AUV_OK;
+    for (const auto &kv : rep) {
+        const int i = kv.second;
+        const auv_batch_item &it = b->items[i];
+        Choice best{b->geom_plain[i].s, auto_algo(it)};
+        float best_ms = 1e30f;
+        for (const Choice &c : candidates(it, b->geom_plain[i].s)) {
+            BinGeom gg;
+            if (bin_geometry(&b->grids[i], it.params.radius, c.bin_log2, &gg) != AUV_OK ||
+                (int64_t)gg.nbx * gg.nby > (int64_t)1 << 24 ||
+                bin_workspace_layout(it.n, gg, nullptr, nullptr) > b->slice_size[i])
+                continue;
+            BinWorkspace w;
+            auv_bin_view bv;
+            IdwArgs a;
+            item_views(b, i, base, gg, c.algo, &w, &bv, &a);
+            float ms_min = 1e30f;
+            for (int rep_i = 0; rep_i < 4; ++rep_i) {
+                AUV_HIP(hipEventRecord(e0, st));
+                result = launch_binning(&b->grids[i], gg, it.x, it.y, it.z, it.n, w, st);
+                if (result == AUV_OK)
+                    result = launch_idw(bv, a, st);
+                AUV_HIP(hipEventRecord(e1, st));
+                AUV_HIP(hipEventSynchronize(e1));
+                if (result != AUV_OK)
+                    break;
+                float ms = 0.0f;
+                AUV_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (rep_i > 0)
+                    ms_min = std::min(ms_min, ms);
+            }
+            if (result != AUV_OK)
+                break;
+            if (ms_min < best_ms) {
+                best_ms = ms_min;
+                best = c;
+            }
+        }
+        if (result != AUV_OK)
+            break;
+        table << "class " << kv.first.dens << " " << kv.first.side << " bin_log2 "
+              << best.bin_log2 << " algo " << best.algo << " ms " << best_ms << "\n";
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (result != AUV_OK)
+        return result;
+    std::ofstream f(tune_path);
+    if (!f)
+        return fail(AUV_ERR_INVALID, std::string("cannot write ") + tune_path);
+    f << table.str();
+    return AUV_OK;
+}
+
+void auv_batch_destroy(auv_batch *b)
+{
+    if (!b)
+        return;
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream)
+        (void)hipStreamDestroy(b->cap_stream);
+    if (b->cap_stream2)
+        (void)hipStreamDestroy(b->cap_stream2);
+    if (b->ev_fork)
+        (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join)
+        (void)hipEventDestroy(b->ev_join);
+    delete b;
+}
+
+}  // extern "C"

@@ -221,13 +221,6 @@ __global__ __launch_bounds__(kThreads) void k_scatter(
     }
 }
 
-struct SoA {
-    int32_t *X, *Y;
-    uint32_t *res;
-    float *z;
-    int32_t *idx;
-};
-
 __device__ inline void emit(const SoA &o, int pos, int orig, const int4 *rec)
 {
     const int4 r = rec[orig];
@@ -320,19 +313,25 @@ constexpr int kRowChunk = 1024;          // soundings per block in k_row_hist
 constexpr int kRowPerThread = kRowChunk / kThreads;
 constexpr int kMaxRowsLds = 8192;        // bin rows in the LDS histogram
 
-__global__ __launch_bounds__(kThreads) void k_row_hist(
-    const double *__restrict__ x, const double *__restrict__ y,
-    const double *__restrict__ z, int64_t n, double x0, double y0, int32_t s,
-    int32_t hB, int32_t nby, double lo, double hix, double hiy,
-    int32_t *__restrict__ row_count, int32_t *__restrict__ rowid,
-    int32_t *__restrict__ pos, int32_t *__restrict__ colkey, int4 *__restrict__ rec,
-    int32_t *__restrict__ drops)
+__device__ void row_hist_block(const RowItem &it, int blk)
 {
+    const double *__restrict__ x = it.x;
+    const double *__restrict__ y = it.y;
+    const double *__restrict__ z = it.z;
+    const int64_t n = it.n;
+    const double x0 = it.x0, y0 = it.y0, lo = it.lo, hix = it.hix, hiy = it.hiy;
+    const int32_t s = it.s, hB = it.hB, nby = it.nby;
+    int32_t *__restrict__ row_count = it.row_count;
+    int32_t *__restrict__ rowid = it.rowid;
+    int32_t *__restrict__ pos = it.pos;
+    int32_t *__restrict__ colkey = it.colkey;
+    int4 *__restrict__ rec = it.rec;
+    int32_t *__restrict__ drops = it.drops;
     __shared__ int s_cnt[kMaxRowsLds];
     for (int r = threadIdx.x; r < nby; r += kThreads)
         s_cnt[r] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kRowChunk + threadIdx.x;
+    const int64_t base = (int64_t)blk * kRowChunk + threadIdx.x;
     int row[kRowPerThread], lr[kRowPerThread];
     int bad = 0, out = 0;
 #pragma unroll
@@ -403,16 +402,20 @@ __global__ __launch_bounds__(kThreads) void k_row_hist(
         block_exclusive_scan(out, lds_b, &tob);
     }
     if (threadIdx.x == 0) {
-        drops[2 * blockIdx.x] = tb;
-        drops[2 * blockIdx.x + 1] = tob;
+        drops[2 * blk] = tb;
+        drops[2 * blk + 1] = tob;
     }
 }
 
 // Exclusive scan of the row counts by one block; also the binned total.
-__global__ __launch_bounds__(kThreads) void k_row_scan(
-    const int32_t *__restrict__ cnt, int32_t nby, int32_t *__restrict__ start,
-    const int32_t *__restrict__ drops, int32_t nblk, unsigned long long *__restrict__ stats)
+__device__ void row_scan_block(const RowItem &it)
 {
+    const int32_t *__restrict__ cnt = it.row_count;
+    const int32_t nby = it.nby;
+    int32_t *__restrict__ start = it.row_start;
+    const int32_t *__restrict__ drops = it.drops;
+    const int32_t nblk = it.nblk;
+    unsigned long long *__restrict__ stats = it.stats;
     __shared__ int lds[kThreads / 64];
     long long nbad = 0, nout = 0;
     for (int b = threadIdx.x; b < nblk; b += kThreads) {
@@ -444,17 +447,14 @@ __global__ __launch_bounds__(kThreads) void k_row_scan(
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_row_scatter(
-    const int32_t *__restrict__ rowid, const int32_t *__restrict__ pos,
-    const int32_t *__restrict__ colkey, int64_t n, const int32_t *__restrict__ row_start,
-    unsigned long long *__restrict__ keys)
+__device__ void row_scatter_block(const RowItem &it, int blk)
 {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i < n) {
-        const int r = rowid[i];
+    const int64_t i = (int64_t)blk * kThreads + threadIdx.x;
+    if (i < it.n) {
+        const int r = it.rowid[i];
         if (r >= 0)
-            keys[row_start[r] + pos[i]] =
-                ((unsigned long long)(uint32_t)colkey[i] << 32) | (uint32_t)i;
+            it.keys[it.row_start[r] + it.pos[i]] =
+                ((unsigned long long)(uint32_t)it.colkey[i] << 32) | (uint32_t)i;
     }
 }
 
@@ -512,15 +512,16 @@ constexpr int kColsLds = 8192;
 constexpr int kSmallRank = 64;      // largest bin ranked member by member
 constexpr int kRowSortLds = 4096;   // keys of a row sorted in LDS
 
-__global__ __launch_bounds__(kThreads) void k_row_sort(
-    unsigned long long *__restrict__ keys, const int32_t *__restrict__ row_start,
-    int32_t nby, int32_t nbx, const int4 *__restrict__ rec, SoA o,
-    int32_t *__restrict__ cell_start, unsigned long long *__restrict__ tmp_keys)
+__device__ void row_sort_block(const RowItem &it, int row, int *s_h,
+                               unsigned long long *s_k, int *lds)
 {
-    __shared__ int s_h[kColsLds];
-    __shared__ unsigned long long s_k[kRowSortLds];
-    __shared__ int lds[kThreads / 64];
-    const int row = blockIdx.x;
+    unsigned long long *__restrict__ keys = it.keys;
+    const int32_t *__restrict__ row_start = it.row_start;
+    const int32_t nby = it.nby, nbx = it.nbx;
+    const int4 *__restrict__ rec = it.rec;
+    const SoA o = it.o;
+    int32_t *__restrict__ cell_start = it.cell_start;
+    unsigned long long *__restrict__ tmp_keys = it.keys2;
     const int r0 = row_start[row], n = row_start[row + 1] - r0;
     for (int bx = threadIdx.x; bx < nbx; bx += kThreads)
         s_h[bx] = 0;
@@ -576,6 +577,84 @@ __global__ __launch_bounds__(kThreads) void k_row_sort(
             rank += tmp_keys[r0 + q] < key ? 1 : 0;
         emit(o, r0 + b0 + rank, (int)(uint32_t)(key & 0xffffffffull), rec);
     }
+}
+
+// Single-item kernels.
+__global__ __launch_bounds__(kThreads) void k_row_fill(RowItem it)
+{
+    for (int r = threadIdx.x; r < it.nby; r += kThreads)
+        it.row_count[r] = 0;
+    if (threadIdx.x < 4)
+        it.stats[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_row_hist(RowItem it) { row_hist_block(it, blockIdx.x); }
+
+__global__ __launch_bounds__(kThreads) void k_row_scan(RowItem it) { row_scan_block(it); }
+
+__global__ __launch_bounds__(kThreads) void k_row_scatter(RowItem it)
+{
+    row_scatter_block(it, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kThreads) void k_row_sort(RowItem it)
+{
+    __shared__ int s_h[kColsLds];
+    __shared__ unsigned long long s_k[kRowSortLds];
+    __shared__ int lds[kThreads / 64];
+    row_sort_block(it, blockIdx.x, s_h, s_k, lds);
+}
+
+// Batched kernels: block b belongs to the item i with off[i] <= b < off[i+1].
+__device__ inline int item_of(const int32_t *off, int count, int b)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kThreads) void k_row_fill_batch(const RowItem *items)
+{
+    const RowItem &it = items[blockIdx.x];
+    for (int r = threadIdx.x; r < it.nby; r += kThreads)
+        it.row_count[r] = 0;
+    if (threadIdx.x < 4)
+        it.stats[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_row_hist_batch(const RowItem *items,
+                                                             const int32_t *off, int count)
+{
+    const int i = item_of(off, count, blockIdx.x);
+    row_hist_block(items[i], blockIdx.x - off[i]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_row_scan_batch(const RowItem *items)
+{
+    row_scan_block(items[blockIdx.x]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_row_scatter_batch(const RowItem *items,
+                                                                const int32_t *off, int count)
+{
+    const int i = item_of(off, count, blockIdx.x);
+    row_scatter_block(items[i], blockIdx.x - off[i]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_row_sort_batch(const RowItem *items,
+                                                             const int32_t *off, int count)
+{
+    __shared__ int s_h[kColsLds];
+    __shared__ unsigned long long s_k[kRowSortLds];
+    __shared__ int lds[kThreads / 64];
+    const int i = item_of(off, count, blockIdx.x);
+    row_sort_block(items[i], blockIdx.x - off[i], s_h, s_k, lds);
 }
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -666,6 +745,44 @@ size_t bin_workspace_layout(int64_t n, const BinGeom &g, char *base, BinWorkspac
     return off;
 }
 
+bool row_path_ok(const BinGeom &geom)
+{
+    return geom.nby <= kMaxRowsLds && geom.nbx <= kColsLds;
+}
+
+RowItem make_row_item(const auv_grid *g, const BinGeom &geom, const double *x,
+                      const double *y, const double *z, int64_t n, const BinWorkspace &w)
+{
+    RowItem it{};
+    it.x = x;
+    it.y = y;
+    it.z = z;
+    it.n = n;
+    it.x0 = g->d.x0;
+    it.y0 = g->d.y0;
+    it.hB = geom.halo << geom.s;
+    it.lo = -(double)it.hB;
+    it.hix = (double)(((int64_t)geom.nbx << geom.s) - it.hB);
+    it.hiy = (double)(((int64_t)geom.nby << geom.s) - it.hB);
+    it.s = geom.s;
+    it.nbx = geom.nbx;
+    it.nby = geom.nby;
+    it.nblk = n > 0 ? (int32_t)grid_for(n, kRowChunk) : 0;
+    it.row_count = w.row_count;
+    it.row_start = w.row_start;
+    it.rowid = w.rowid;
+    it.pos = w.slot;
+    it.colkey = w.key;
+    it.drops = w.partials;
+    it.cell_start = w.cell_start;
+    it.rec = w.rec;
+    it.keys = w.keys;
+    it.keys2 = w.keys2;
+    it.stats = reinterpret_cast<unsigned long long *>(w.stats);
+    it.o = SoA{w.X, w.Y, w.res, w.z, w.idx};
+    return it;
+}
+
 auv_status launch_binning(const auv_grid *g, const BinGeom &geom, const double *x,
                           const double *y, const double *z, int64_t n,
                           const BinWorkspace &w, hipStream_t st)
@@ -678,26 +795,19 @@ auv_status launch_binning(const auv_grid *g, const BinGeom &geom, const double *
     const double hiy = (double)(((int64_t)geom.nby << geom.s) - hB);
     auto *stats = reinterpret_cast<unsigned long long *>(w.stats);
 
-    k_fill_i64<<<1, 64, 0, st>>>(w.stats, 4);
-    if (geom.nby <= kMaxRowsLds && geom.nbx <= kColsLds) {
-        SoA o{w.X, w.Y, w.res, w.z, w.idx};
-        k_fill_i32<<<(unsigned)std::min<int64_t>(grid_for(geom.nby, kThreads), 64), kThreads,
-                     0, st>>>(w.row_count, geom.nby, 0);
-        const int nblk = n > 0 ? (int)grid_for(n, kRowChunk) : 0;
+    if (row_path_ok(geom)) {
+        const RowItem it = make_row_item(g, geom, x, y, z, n, w);
+        k_row_fill<<<1, kThreads, 0, st>>>(it);
         if (n > 0)
-            k_row_hist<<<nblk, kThreads, 0, st>>>(
-                x, y, z, n, g->d.x0, g->d.y0, geom.s, hB, geom.nby, lo, hix, hiy,
-                w.row_count, w.rowid, w.slot, w.key, w.rec, w.partials);
-        k_row_scan<<<1, kThreads, 0, st>>>(w.row_count, geom.nby, w.row_start, w.partials, nblk,
-                                           stats);
+            k_row_hist<<<it.nblk, kThreads, 0, st>>>(it);
+        k_row_scan<<<1, kThreads, 0, st>>>(it);
         if (n > 0)
-            k_row_scatter<<<grid_for(n, kThreads), kThreads, 0, st>>>(
-                w.rowid, w.slot, w.key, n, w.row_start, w.keys);
-        k_row_sort<<<(unsigned)geom.nby, kThreads, 0, st>>>(
-            w.keys, w.row_start, geom.nby, geom.nbx, w.rec, o, w.cell_start, w.keys2);
+            k_row_scatter<<<grid_for(n, kThreads), kThreads, 0, st>>>(it);
+        k_row_sort<<<(unsigned)geom.nby, kThreads, 0, st>>>(it);
         AUV_HIP(hipGetLastError());
         return AUV_OK;
     }
+    k_fill_i64<<<1, 64, 0, st>>>(w.stats, 4);
     k_fill_i32<<<(unsigned)std::min<int64_t>(grid_for(nb, kThreads), 4096), kThreads, 0, st>>>(
         w.counts, nb, 0);
     if (n > 0) {
@@ -720,6 +830,28 @@ auv_status launch_binning(const auv_grid *g, const BinGeom &geom, const double *
                           kThreads, 0, st>>>(w.cell_start, w.perm_tmp, w.rec, o,
                                              w.big_list, stats);
     }
+    AUV_HIP(hipGetLastError());
+    return AUV_OK;
+}
+
+
+int32_t row_hist_blocks(int64_t n) { return n > 0 ? (int32_t)grid_for(n, kRowChunk) : 0; }
+int32_t row_scatter_blocks(int64_t n) { return n > 0 ? (int32_t)grid_for(n, kThreads) : 0; }
+
+auv_status launch_binning_batch(const RowItem *d_items, const int32_t *d_hist_off,
+                                const int32_t *d_scatter_off, const int32_t *d_sort_off,
+                                int32_t count, int32_t hist_blocks, int32_t scatter_blocks,
+                                int32_t sort_blocks, hipStream_t st)
+{
+    if (count <= 0)
+        return AUV_OK;
+    k_row_fill_batch<<<count, kThreads, 0, st>>>(d_items);
+    if (hist_blocks > 0)
+        k_row_hist_batch<<<hist_blocks, kThreads, 0, st>>>(d_items, d_hist_off, count);
+    k_row_scan_batch<<<count, kThreads, 0, st>>>(d_items);
+    if (scatter_blocks > 0)
+        k_row_scatter_batch<<<scatter_blocks, kThreads, 0, st>>>(d_items, d_scatter_off, count);
+    k_row_sort_batch<<<sort_blocks, kThreads, 0, st>>>(d_items, d_sort_off, count);
     AUV_HIP(hipGetLastError());
     return AUV_OK;
 }

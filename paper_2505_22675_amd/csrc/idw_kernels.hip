@@ -353,8 +353,9 @@ __global__ __launch_bounds__(64) void k_idw_tile(auv_bin_view bv, IdwArgs a,
 
 }  // namespace
 
-auv_status launch_idw(const auv_bin_view &bv, const IdwArgs &a, hipStream_t st)
+auv_status launch_idw(const auv_bin_view &bv, const IdwArgs &a_in, hipStream_t st)
 {
+    IdwArgs a = a_in;
     const int ntx = (a.nx + kTW - 1) / kTW, nty = (a.ny + kTH - 1) / kTH;
     const int64_t ntiles = (int64_t)ntx * nty;
     if (ntiles > INT_MAX)
@@ -366,6 +367,7 @@ auv_status launch_idw(const auv_bin_view &bv, const IdwArgs &a, hipStream_t st)
         pmode = 2;
     else if (a.power == 3.0f)
         pmode = 3;
+    a.pmode = pmode;
     if (a.dense)
         return launch_idw_dense(bv, a, pmode, st);
     WinGeom wg;

@@ -279,7 +279,7 @@ __device__ void exact_node(const auv_bin_view &bv, const IdwArgs &a, int X0, int
                 hsum += (double)z;
             }
             if constexpr (kPmode != 0) {
-                const float w = weight_fast(d2f, kPmode);
+                const float w = weight_fast(d2f, kPmode > 0 ? kPmode : a.pmode);
                 num += w * (z - zref);
                 den += w;
             } else {
@@ -349,9 +349,21 @@ constexpr int kAcc = kTN * kRS;
 // by one from their lane (readlane -> SGPRs).  The only LDS traffic in the
 // visit loop is then the fire-and-forget accumulator updates, so nothing in
 // the loop waits on LDS.
+// Shared arrays of one window tile (pointers into the caller's LDS).
+struct WinSmem {
+    float2 *nd;                 // numerator, denominator        [kAcc]
+    int *cnt;                   // members                       [kAcc]
+    unsigned long long *key;    // packed (D^2 << b) | index     [kAcc] (packed)
+    double *bd2;                // best D^2                      [kAcc] (unpacked)
+    int *bidx;                  // best index                    [kAcc] (unpacked)
+    float *bz;                  // best depth                    [kAcc] (unpacked)
+    float *emax;                // running log2 weight max       [kAcc] (general p)
+    int *beg, *off;             // staging rows                  [kMaxRows(+1)]
+};
+
 template <int kMode, int kPmode, bool kPacked, int kChunks, int kPrec>
-__global__ __launch_bounds__(64) void k_idw_window(auv_bin_view bv, IdwArgs a, WinGeom g,
-                                                    int ntx, int nty)
+__device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinGeom &g,
+                            int tile, int ntx, const WinSmem &sm)
 {
     constexpr bool kIdw = (kMode & 1) != 0;
     // Accumulators are updated by plain LDS read-modify-write: within one
@@ -359,18 +371,17 @@ __global__ __launch_bounds__(64) void k_idw_window(auv_bin_view bv, IdwArgs a, W
     // complete in order, so no atomics are needed (LDS atomics would serialise
     // per lane).
     constexpr bool kAtomic = false;
-    __shared__ float2 s_nd[kAcc];      // numerator, denominator
-    __shared__ int s_cnt[kAcc];
-    __shared__ unsigned long long s_key[kPacked ? kAcc : 1];   // (D^2 << b) | index
-    __shared__ double s_bd2[kPacked ? 1 : kAcc];
-    __shared__ int s_bidx[kPacked ? 1 : kAcc];
-    __shared__ float s_bz[kPacked ? 1 : kAcc];
-    __shared__ float s_emax[kPmode == 0 ? kAcc : 1];
-    __shared__ int s_beg[kMaxRows];
-    __shared__ int s_off[kMaxRows + 1];
+    float2 *const s_nd = sm.nd;
+    int *const s_cnt = sm.cnt;
+    unsigned long long *const s_key = sm.key;
+    double *const s_bd2 = sm.bd2;
+    int *const s_bidx = sm.bidx;
+    float *const s_bz = sm.bz;
+    float *const s_emax = sm.emax;
+    int *const s_beg = sm.beg;
+    int *const s_off = sm.off;
 
     const int lane = threadIdx.x;
-    const int tile = xcd_tile(blockIdx.x, ntx * nty);
     const int tx = tile % ntx, ty = tile / ntx;
     const int tb0 = tx * kTN, ta0 = ty * kTN;
     const int tw = min(kTN, a.nx - tb0), th = min(kTN, a.ny - ta0);
@@ -394,6 +405,7 @@ __global__ __launch_bounds__(64) void k_idw_window(auv_bin_view bv, IdwArgs a, W
         qo[t] = v ? ci[t] * kRS + cj[t] : 0;
     }
 
+    __syncthreads();  // the previous tile of this wave is finished with LDS
     for (int q = lane; q < kAcc; q += 64) {
         s_nd[q] = make_float2(0.0f, 0.0f);
         s_cnt[q] = 0;
@@ -537,7 +549,8 @@ __global__ __launch_bounds__(64) void k_idw_window(auv_bin_view bv, IdwArgs a, W
                         float w = 0.0f;
                         if constexpr (kIdw) {
                             if constexpr (kPmode != 0)
-                                w = D2 == 0 ? kHitW : weight_fast(d2f, kPmode);
+                                w = D2 == 0 ? kHitW
+                                            : weight_fast(d2f, kPmode > 0 ? kPmode : a.pmode);
                             else
                                 w = D2 == 0 ? 1e30f : log_weight(d2f * a.inv_r2, a.power);
                         }
@@ -650,6 +663,25 @@ __global__ __launch_bounds__(64) void k_idw_window(auv_bin_view bv, IdwArgs a, W
                                              tb0 + qn % kTN, zref);
         }
     }
+}
+
+
+template <int kMode, int kPmode, bool kPacked, int kChunks, int kPrec>
+__global__ __launch_bounds__(64) void k_idw_window(auv_bin_view bv, IdwArgs a, WinGeom g,
+                                                    int ntx, int nty)
+{
+    __shared__ float2 s_nd[kAcc];
+    __shared__ int s_cnt[kAcc];
+    __shared__ unsigned long long s_key[kPacked ? kAcc : 1];
+    __shared__ double s_bd2[kPacked ? 1 : kAcc];
+    __shared__ int s_bidx[kPacked ? 1 : kAcc];
+    __shared__ float s_bz[kPacked ? 1 : kAcc];
+    __shared__ float s_emax[kPmode == 0 ? kAcc : 1];
+    __shared__ int s_beg[kMaxRows];
+    __shared__ int s_off[kMaxRows + 1];
+    const WinSmem sm{s_nd, s_cnt, s_key, s_bd2, s_bidx, s_bz, s_emax, s_beg, s_off};
+    window_tile<kMode, kPmode, kPacked, kChunks, kPrec>(
+        bv, a, g, xcd_tile(blockIdx.x, ntx * nty), ntx, sm);
 }
 
 template <int kMode, bool kPacked, int kChunks, int kPrec>

@@ -58,3 +58,72 @@ def test_workspace_query_on_host():
     with pytest.raises(ag.AuvError):
         ag.auv_bin_workspace_size(g, -5, 6.0, 0)
     assert "radius" in ag.auv_last_error() or "n must" in ag.auv_last_error()
+
+
+def _host_item(n=1000, side=64, power=2.0, precision=ag.AUV_P_FP32_REBASE, max_pts=16):
+    # placeholder addresses: planning validates and sizes, it never dereferences
+    it = ag.auv_batch_item()
+    it.grid = ag.make_desc(0, 0, 2.0, 2.0, side, side)
+    it.x, it.y, it.z = 0x10000, 0x20000, 0x30000
+    it.n = n
+    it.params = ag.idw_params(power, 6.0, 1, max_pts, precision)
+    it.z_out = 0x40000
+    return it
+
+
+def test_batch_plan_on_host():
+    lib = ag.load_library()
+    items = [_host_item(200_000, 64), _host_item(1_000, 1024, power=1.5),
+             _host_item(0, 128, max_pts=0)]
+    arr = (ag.auv_batch_item * 3)(*items)
+    h = ctypes.c_void_p()
+    assert lib.auv_batch_plan(arr, 3, None, ctypes.byref(h)) == ag.AUV_OK
+    nbytes = ctypes.c_size_t()
+    assert lib.auv_batch_workspace_size(h, ctypes.byref(nbytes)) == ag.AUV_OK
+    # at least the binned records of every item
+    assert nbytes.value > 201_000 * 40
+    s, a = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.auv_batch_item_plan(h, 0, ctypes.byref(s), ctypes.byref(a)) == ag.AUV_OK
+    # ~1150 soundings per disk with k = 16: the dense form by default
+    assert (s.value, a.value) == (19, ag.AUV_ALGO_DENSE)
+    assert lib.auv_batch_item_plan(h, 1, ctypes.byref(s), ctypes.byref(a)) == ag.AUV_OK
+    assert (s.value, a.value) == (19, ag.AUV_ALGO_SPARSE)
+    assert lib.auv_batch_item_plan(h, 3, ctypes.byref(s), ctypes.byref(a)) == ag.AUV_ERR_INVALID
+    lib.auv_batch_destroy(h)
+
+
+def test_batch_plan_reads_tune_table(tmp_path):
+    lib = ag.load_library()
+    items = [_host_item(200_000, 64)]
+    # class of the item: floor(log2(disk population + 1)), round(log2(side))
+    pop = 200_000 / (128.0 + 12.0) ** 2 * 3.141592653589793 * 36.0
+    dens = int(__import__("math").floor(__import__("math").log2(pop + 1.0)))
+    table = tmp_path / "tune.txt"
+    table.write_text("# comment line\n"
+                     f"class {dens} 6 bin_log2 17 algo {ag.AUV_ALGO_SPARSE} ms 0.1\n")
+    arr = (ag.auv_batch_item * 1)(*items)
+    h = ctypes.c_void_p()
+    assert lib.auv_batch_plan(arr, 1, str(table).encode(), ctypes.byref(h)) == ag.AUV_OK
+    s, a = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.auv_batch_item_plan(h, 0, ctypes.byref(s), ctypes.byref(a)) == ag.AUV_OK
+    assert (s.value, a.value) == (17, ag.AUV_ALGO_SPARSE)
+    lib.auv_batch_destroy(h)
+
+
+def test_batch_plan_rejects_bad_items():
+    lib = ag.load_library()
+    bad = [_host_item(), _host_item(precision=ag.AUV_P_FP16_OFFSETS)]
+    arr = (ag.auv_batch_item * 2)(*bad)
+    h = ctypes.c_void_p()
+    assert lib.auv_batch_plan(arr, 2, None, ctypes.byref(h)) == ag.AUV_ERR_INVALID
+    assert "item 1" in ag.auv_last_error()
+    assert not h.value
+    bad = [_host_item(power=-1.0)]
+    arr = (ag.auv_batch_item * 1)(*bad)
+    assert lib.auv_batch_plan(arr, 1, None, ctypes.byref(h)) == ag.AUV_ERR_INVALID
+    assert "item 0" in ag.auv_last_error()
+    assert lib.auv_batch_plan(arr, 0, None, ctypes.byref(h)) == ag.AUV_ERR_INVALID
+    it = _host_item()
+    it.z_out = None
+    arr = (ag.auv_batch_item * 1)(it)
+    assert lib.auv_batch_plan(arr, 1, None, ctypes.byref(h)) == ag.AUV_ERR_INVALID
