@@ -145,6 +145,147 @@ def precision_report(ag, dev):
     return out
 
 
+def batched_report(ag, dev, reps=20):
+    """256 uneven tiles (1e3..2e5 soundings, 64^2..1024^2 nodes, p in {1,2,3}):
+    the plain form (tile after tile, default bin size and kernel choice, no
+    graph) against the batched form (autotuned per tile class, batched
+    binning, persistent kernels, one HIP graph)."""
+    import tempfile
+
+    import numpy as np
+    import torch
+
+    from gen import checksum, workload_cfg3_tiles
+
+    log("generating 256-tile batched workload")
+    tiles = workload_cfg3_tiles()
+    keep, items = [], []
+    n_pts = n_nodes = 0
+    for s in tiles:
+        x, y, z = (torch.from_numpy(a).to(dev) for a in (s.x, s.y, s.z))
+        shape = (s.grid.ny, s.grid.nx)
+        zo = torch.empty(shape, dtype=torch.float32, device=dev)
+        no = torch.empty(shape, dtype=torch.int32, device=dev)
+        nz = torch.empty(shape, dtype=torch.float32, device=dev)
+        desc = ag.make_desc(s.grid.x0, s.grid.y0, s.grid.dx, s.grid.dy, s.grid.nx, s.grid.ny)
+        p = ag.idw_params(s.power, s.radius, s.min_pts, s.max_pts)
+        items.append(ag.batch_item(desc, x, y, z, p, zo, None, no, nz))
+        keep.append((x, y, z, zo, no, nz))
+        n_pts += s.n
+        n_nodes += s.grid.nx * s.grid.ny
+    plain = ag.Batch(items)
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "tune.txt")
+        t0 = time.perf_counter()
+        ag.auv_batch_autotune(items, plain.ws, path)
+        tune_s = time.perf_counter() - t0
+        tuned = ag.Batch(items, tune_path=path)
+        table = [ln.strip() for ln in open(path) if ln.startswith("class ")]
+    plans = [tuned.item_plan(i) for i in range(len(items))]
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(reps)]
+        for e0, e1 in evs:
+            e0.record()
+            fn()
+            e1.record()
+        torch.cuda.synchronize()
+        ms = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+        return float(np.median(ms)), float(ms.min())
+
+    plain_med, plain_min = timed(plain.launch_plain)
+    batch_med, batch_min = timed(tuned.launch)
+    log(f"batched workload: plain {plain_med:.3f} ms, batched {batch_med:.3f} ms "
+        f"(median of {reps})")
+    alg_bytes = n_pts * 24 + n_nodes * 12
+    out = {
+        "workload": "256 uneven tiles: soundings log-uniform 1e3..2e5, side in "
+                    "{64..1024} @ 2 m, p in {1,2,3}, r=6 m, k=16, min 1; IDW + nearest",
+        "soundings": int(n_pts), "nodes": int(n_nodes),
+        "input_sha": checksum(*[a for s in tiles for a in (s.x, s.y, s.z)]),
+        "plain_ms": round(plain_med, 4), "plain_min_ms": round(plain_min, 4),
+        "batched_ms": round(batch_med, 4), "batched_min_ms": round(batch_min, 4),
+        "speedup": round(plain_med / batch_med, 3),
+        "plain_nodes_per_s": round(n_nodes / (plain_med * 1e-3), 1),
+        "batched_nodes_per_s": round(n_nodes / (batch_med * 1e-3), 1),
+        "batched_hbm_frac": round(alg_bytes / (batch_med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "algorithmic_bytes": int(alg_bytes),
+        "autotune_s": round(tune_s, 2), "tune_table": table,
+        "dense_tiles": int(sum(a == ag.AUV_ALGO_DENSE for _, a in plans)),
+    }
+    plain.close()
+    tuned.close()
+    del keep
+    return out
+
+
+def serving_report(ag, dev, duration=3.0, stress=10.0):
+    """16 vehicles (2048^2 grids at 2 m), Poisson requests at 20 Hz per vehicle
+    of 2k..50k soundings (a +-60 deg fan at 150 m altitude), replayed in real
+    time: FIFO (one request at a time) against continuous batching, at the
+    nominal rate and at `stress` times the rate (same requests, arrival times
+    divided).  Latency = completion seen by the session - scheduled arrival."""
+    import numpy as np
+    import torch
+
+    from gen import serving_schedule
+
+    log(f"generating {duration:.0f} s of serving requests")
+    grids, reqs = serving_schedule(duration=duration)
+    n_req = len(reqs)
+    n_snd = int(sum(len(r.x) for r in reqs))
+    out = {"workload": f"16 vehicles, 2048^2 grids @ 2 m, Poisson 20 Hz each, 2k..50k "
+                       f"soundings per request, r=6 m p=2 no cap; {duration:.0f} s replay",
+           "requests": n_req, "soundings": n_snd}
+    for mode, name in ((ag.AUV_SERVE_FIFO, "fifo"), (ag.AUV_SERVE_BATCHED, "batched")):
+        for scale in (1.0, stress):
+            desc = ag.session_desc(grids, power=2.0, radius=6.0, min_pts=1, max_request=50000,
+                                   slots=64, mode=mode, z_ref=[-5000.0] * len(grids))
+            fixed, per_v = ag.auv_session_budget(desc)
+            arena = torch.empty(fixed + len(grids) * per_v, dtype=torch.uint8, device=dev)
+            sess = ag.Session(desc, arena)
+            empty = np.zeros(0)
+            for v in range(len(grids)):      # admit every vehicle, load the kernels
+                sess.submit(v, empty, empty, empty)
+            sess.drain()
+            t0 = sess.now() + 0.05
+            tickets = []
+            for r in reqs:
+                ta = t0 + r.t_arrival / scale
+                while True:
+                    d = ta - sess.now()
+                    if d <= 0:
+                        break
+                    if d > 2e-3:
+                        time.sleep(d - 1e-3)
+                tickets.append(sess.submit(r.vehicle, r.x, r.y, r.z, t_arrival=ta))
+            sess.drain()
+            infos = [sess.poll(t) for t in tickets]
+            lat = np.array([i.t_done - i.t_arrival for i in infos]) * 1e3
+            queue = np.array([i.t_launch - i.t_arrival for i in infos]) * 1e3
+            late = max(i.t_done for i in infos) - t0
+            updates = 0
+            for v in range(len(grids)):
+                _, c = sess.read_grid(v)
+                updates += int(c.sum().item())
+            sess.close()
+            del arena
+            key = f"{name}_x{int(scale)}"
+            out[key] = {"p50_ms": round(float(np.percentile(lat, 50)), 4),
+                        "p99_ms": round(float(np.percentile(lat, 99)), 4),
+                        "max_ms": round(float(lat.max()), 4),
+                        "queue_p99_ms": round(float(np.percentile(queue, 99)), 4),
+                        "node_updates": updates,
+                        "node_updates_per_s": round(updates / late, 1),
+                        "soundings_per_s": round(n_snd / late, 1)}
+            log(f"serving {key}: p50 {out[key]['p50_ms']:.3f} ms, p99 {out[key]['p99_ms']:.3f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +294,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the UTM-scale precision-variant error report")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 256-tile plain-vs-batched comparison")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the 16-vehicle serving replay (FIFO vs continuous batching)")
+    ap.add_argument("--serving-seconds", type=float, default=3.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -256,6 +402,14 @@ def main():
     if not args.no_precision:
         precision = precision_report(ag, dev)
 
+    batched = None
+    if not args.no_batched:
+        batched = batched_report(ag, dev)
+
+    serving = None
+    if not args.no_serving:
+        serving = serving_report(ag, dev, duration=args.serving_seconds)
+
     value = nodes / (ms_per_step * 1e-3)
     rec = {
         "metric": METRIC, "value": round(value, 1), "unit": "grid nodes/s", "n_gpus": 1,
@@ -272,6 +426,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "precision_utm": precision,
+        "batched_tiles": batched,
+        "serving": serving,
     }
     print(json.dumps(rec), flush=True)
 

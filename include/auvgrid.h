@@ -255,6 +255,103 @@ auv_status auv_batch_item_plan(const auv_batch *batch, int32_t item, int32_t *bi
 
 void auv_batch_destroy(auv_batch *batch);
 
+/* ------------------------------------------------------------ serving --
+ * Real-time gridding of many vehicles' sounding streams with the grids kept
+ * on the device; the host only controls (the real-time mode of Sec. IV).
+ * Each vehicle owns a grid and resident per-node sums of the radius-limited
+ * IDW (no k-cap, so the sums are additive): weighted depth, weight, count;
+ * a coincident sounding adds a dominant weight, so the read-out of a node
+ * with hits is the mean of its hits.  A request (a block of soundings from one
+ * vehicle) is rebased, binned and gathered into the sums of the nodes within
+ * the radius; reading a grid finalizes z = z_ref + sum(w dz) / sum(w) (NaN
+ * where count < min_pts and no hit).  After any set of requests the read-out
+ * equals auv_interp_idw (max_pts 0) on the union of that vehicle's soundings,
+ * within the same tolerance.  A vehicle's requests are applied in submission
+ * order, one per launch, so its grid does not depend on the other vehicles'
+ * traffic or on the batching (bit for bit).
+ *
+ * A worker thread owned by the session drains the queue on its own stream:
+ * AUV_SERVE_FIFO runs one request at a time and waits for it;
+ * AUV_SERVE_BATCHED (continuous batching) launches every queued request it
+ * can (at most one per vehicle and max_batch per launch) as one batched
+ * launch, keeps two launches in flight and forms the next batch while the
+ * GPU works. */
+enum { AUV_SERVE_FIFO = 0, AUV_SERVE_BATCHED = 1 };
+enum { AUV_T_QUEUED = 0, AUV_T_RUNNING = 1, AUV_T_DONE = 2, AUV_T_FAILED = 3 };
+
+typedef struct {
+    int32_t n_vehicles;
+    const auv_grid_desc *grids; /* host [n_vehicles] */
+    const double *z_ref;        /* host [n_vehicles] reference depth per vehicle, nullable (0) */
+    auv_idw_params params;      /* power 1, 2 or 3; max_pts 0; precision AUV_P_FP32_REBASE;
+                                   the node spacing times 2^16 must be an even integer and
+                                   (2 r / dx + 1)(2 r / dy + 1) <= 256 */
+    int32_t max_request;        /* soundings per request, 1 .. 2^24 */
+    int32_t slots;              /* requests held at once (queued or running), 1 .. 4096 */
+    int32_t mode;               /* AUV_SERVE_FIFO or AUV_SERVE_BATCHED */
+    int32_t max_batch;          /* requests per batched launch, 1 .. 64 (0: 64) */
+} auv_session_desc;
+
+typedef struct {
+    int32_t state;              /* AUV_T_* */
+    int32_t vehicle;
+    int64_t n;
+    double t_arrival;           /* as given to auv_session_submit */
+    double t_launch;            /* session clock when its launch was enqueued */
+    double t_done;              /* session clock when its completion was observed */
+} auv_ticket_info;
+
+typedef struct auv_session auv_session;
+
+/* Device bytes a session needs: `fixed` for the request slots' staging and
+ * binning space and the launch tables, plus `per_vehicle` (12 bytes per node
+ * of the largest grid) for each admitted vehicle.  Host only. */
+auv_status auv_session_budget(const auv_session_desc *desc, size_t *fixed,
+                              size_t *per_vehicle);
+
+/* Create a session on the current device.  `arena` (device, 256-byte aligned,
+ * caller-owned, at least `fixed` bytes) is the session's whole HBM budget:
+ * slots, tables and every admitted vehicle's sums are carved from it.
+ * Allocates pinned host staging (slots x max_request soundings).  Errors:
+ * AUV_ERR_INVALID for a bad descriptor, AUV_ERR_BUDGET when the arena cannot
+ * hold the fixed part. */
+auv_status auv_session_create(const auv_session_desc *desc, void *arena, size_t arena_bytes,
+                              auv_session **out);
+
+/* Queue one request of n soundings (host float64 arrays, copied before the
+ * call returns) for `vehicle`.  A vehicle is admitted at its first request:
+ * its sums are carved from the arena and cleared; when the arena cannot hold
+ * them the call fails with AUV_ERR_BUDGET and queues nothing.  Blocks while
+ * every slot is taken.  t_arrival is the request's arrival on the session
+ * clock (auv_session_now), kept for latency reports.  Thread-safe. */
+auv_status auv_session_submit(auv_session *s, int32_t vehicle, const double *x,
+                              const double *y, const double *z, int64_t n, double t_arrival,
+                              uint64_t *ticket);
+
+/* State and times of a ticket.  Thread-safe. */
+auv_status auv_session_poll(auv_session *s, uint64_t ticket, auv_ticket_info *info);
+
+/* Block until every request submitted so far has finished.  Returns
+ * AUV_ERR_HIP if any of them failed. */
+auv_status auv_session_drain(auv_session *s);
+
+/* Wait for the vehicle's submitted requests, then enqueue the read-out of its
+ * grid on `stream`: z_out device float [ny][nx] (NaN: no value), cnt_out
+ * device int32 [ny][nx] (nullable; soundings within the radius so far). */
+auv_status auv_session_read_grid(auv_session *s, int32_t vehicle, float *z_out,
+                                 int32_t *cnt_out, auv_stream stream);
+
+/* Wait for the vehicle's requests and release its sums back to the arena
+ * (its grid is lost; a later request admits it again, empty).  Work the
+ * caller enqueued on other streams that reads the vehicle must be finished. */
+auv_status auv_session_retire(auv_session *s, int32_t vehicle);
+
+/* Seconds since the session was created (steady clock). */
+double auv_session_now(const auv_session *s);
+
+/* Drain, stop the worker and free host-side resources (not the arena). */
+void auv_session_destroy(auv_session *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,6 +60,26 @@ class auv_batch_item(ctypes.Structure):
                 ("nn_idx_out", ctypes.c_void_p), ("nn_z_out", ctypes.c_void_p)]
 
 
+AUV_SERVE_FIFO = 0
+AUV_SERVE_BATCHED = 1
+AUV_T_QUEUED, AUV_T_RUNNING, AUV_T_DONE, AUV_T_FAILED = 0, 1, 2, 3
+
+
+class auv_session_desc(ctypes.Structure):
+    _fields_ = [("n_vehicles", ctypes.c_int32),
+                ("grids", ctypes.POINTER(auv_grid_desc)),
+                ("z_ref", ctypes.POINTER(ctypes.c_double)),
+                ("params", auv_idw_params),
+                ("max_request", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+
+
+class auv_ticket_info(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("vehicle", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("t_arrival", ctypes.c_double), ("t_launch", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -98,6 +118,16 @@ def load_library(path: str = LIB_PATH):
                                 ctypes.c_char_p], ctypes.c_int),
         "auv_batch_item_plan": ([vp, i32, P(i32), P(i32)], ctypes.c_int),
         "auv_batch_destroy": ([vp], None),
+        "auv_session_budget": ([P(auv_session_desc), P(ctypes.c_size_t), P(ctypes.c_size_t)],
+                               ctypes.c_int),
+        "auv_session_create": ([P(auv_session_desc), vp, ctypes.c_size_t, P(vp)], ctypes.c_int),
+        "auv_session_submit": ([vp, i32, vp, vp, vp, i64, d, P(ctypes.c_uint64)], ctypes.c_int),
+        "auv_session_poll": ([vp, ctypes.c_uint64, P(auv_ticket_info)], ctypes.c_int),
+        "auv_session_drain": ([vp], ctypes.c_int),
+        "auv_session_read_grid": ([vp, i32, vp, vp, vp], ctypes.c_int),
+        "auv_session_retire": ([vp, i32], ctypes.c_int),
+        "auv_session_now": ([vp], d),
+        "auv_session_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -395,3 +425,108 @@ def auv_batch_autotune(items, ws: torch.Tensor, tune_path: str, stream=None):
     arr = _items_array(items)
     _check(lib.auv_batch_autotune(arr, len(items), _dev(ws, torch.uint8, "ws"), ws.numel(),
                                   _stream(stream), tune_path.encode()))
+
+
+# ------------------------------------------------------------------ serving
+
+
+def session_desc(grids, power=2.0, radius=6.0, min_pts=1, max_request=50000, slots=32,
+                 mode=AUV_SERVE_BATCHED, max_batch=0, z_ref=None) -> auv_session_desc:
+    """Build an ``auv_session_desc``; grids: objects with x0, y0, dx, dy, nx, ny.
+    The returned struct keeps its arrays alive (``_keep``)."""
+    g = (auv_grid_desc * len(grids))()
+    for i, gr in enumerate(grids):
+        g[i] = gr if isinstance(gr, auv_grid_desc) else make_desc(gr.x0, gr.y0, gr.dx, gr.dy,
+                                                                   gr.nx, gr.ny)
+    d = auv_session_desc()
+    d.n_vehicles = len(grids)
+    d.grids = g
+    zr = None
+    if z_ref is not None:
+        zr = (ctypes.c_double * len(grids))(*[float(v) for v in z_ref])
+        d.z_ref = zr
+    d.params = idw_params(power, radius, min_pts, 0)
+    d.max_request = int(max_request)
+    d.slots = int(slots)
+    d.mode = int(mode)
+    d.max_batch = int(max_batch)
+    d._keep = (g, zr)
+    return d
+
+
+def auv_session_budget(desc: auv_session_desc):
+    """(fixed bytes, bytes per admitted vehicle)."""
+    lib = load_library()
+    f, v = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib.auv_session_budget(ctypes.byref(desc), ctypes.byref(f), ctypes.byref(v)))
+    return int(f.value), int(v.value)
+
+
+def _host_f64(a, name):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim != 1:
+        raise ValueError(f"{name} must be one-dimensional")
+    return a
+
+
+class Session:
+    """Owning wrapper of an ``auv_session*``; the arena is a uint8 device tensor."""
+
+    def __init__(self, desc: auv_session_desc, arena: torch.Tensor):
+        lib = load_library()
+        self.desc = desc
+        self.arena = arena
+        if not arena.is_cuda or arena.dtype != torch.uint8:
+            raise ValueError("arena must be a uint8 device tensor")
+        h = ctypes.c_void_p()
+        _check(lib.auv_session_create(ctypes.byref(desc), ctypes.c_void_p(arena.data_ptr()),
+                                      arena.numel(), ctypes.byref(h)))
+        self._h = h
+        self.grids = [desc.grids[i] for i in range(desc.n_vehicles)]
+
+    def now(self) -> float:
+        return float(_lib.auv_session_now(self._h))
+
+    def submit(self, vehicle: int, x, y, z, t_arrival=None) -> int:
+        x, y, z = _host_f64(x, "x"), _host_f64(y, "y"), _host_f64(z, "z")
+        n = x.shape[0]
+        if y.shape[0] != n or z.shape[0] != n:
+            raise ValueError("x, y, z lengths differ")
+        t = ctypes.c_uint64()
+        ta = self.now() if t_arrival is None else float(t_arrival)
+        _check(_lib.auv_session_submit(self._h, int(vehicle), x.ctypes.data, y.ctypes.data,
+                                       z.ctypes.data, n, ta, ctypes.byref(t)))
+        return int(t.value)
+
+    def poll(self, ticket: int) -> auv_ticket_info:
+        info = auv_ticket_info()
+        _check(_lib.auv_session_poll(self._h, ticket, ctypes.byref(info)))
+        return info
+
+    def drain(self):
+        _check(_lib.auv_session_drain(self._h))
+
+    def read_grid(self, vehicle: int, with_counts=True, stream=None):
+        g = self.grids[vehicle]
+        dev = self.arena.device
+        z = torch.empty((g.ny, g.nx), dtype=torch.float32, device=dev)
+        c = torch.empty((g.ny, g.nx), dtype=torch.int32, device=dev) if with_counts else None
+        _check(_lib.auv_session_read_grid(self._h, int(vehicle), ctypes.c_void_p(z.data_ptr()),
+                                          ctypes.c_void_p(c.data_ptr()) if c is not None else None,
+                                          _stream(stream)))
+        return z, c
+
+    def retire(self, vehicle: int):
+        _check(_lib.auv_session_retire(self._h, int(vehicle)))
+
+    def close(self):
+        if self._h:
+            _lib.auv_session_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

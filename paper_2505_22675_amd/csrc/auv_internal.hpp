@@ -130,6 +130,21 @@ struct RowItem {
     SoA o;
 };
 
+// Batched launches: block b belongs to the item i with off[i] <= b < off[i+1]
+// (off ascending, count items; empty items have off[i] == off[i+1]).
+__device__ inline int item_of(const int32_t *off, int count, int b)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 bool row_path_ok(const BinGeom &geom);
 RowItem make_row_item(const auv_grid *g, const BinGeom &geom, const double *x,
                       const double *y, const double *z, int64_t n, const BinWorkspace &w);
@@ -153,7 +168,8 @@ struct IdwArgs {
     float power;
     int32_t min_pts, max_pts;
     int32_t precision;
-    int32_t mode;             // bit 0: IDW value, bit 1: nearest outputs
+    int32_t mode;             // bit 0: IDW value, bit 1: nearest outputs,
+                              // bit 2: accumulate into acc_* (serving)
     float inv_r2;             // 1 / R^2 (lattice units)
     int32_t R_stage;          // lattice reach of the candidate search (>= R)
     float r2f;                // radius^2 in m^2, FP32 (precision variants)
@@ -164,6 +180,11 @@ struct IdwArgs {
     int32_t *cnt_out;
     int32_t *nn_idx_out;
     float *nn_z_out;
+    // accumulate mode: resident sums over all requests so far, depths
+    // relative to zref_acc
+    float *acc_num, *acc_den;
+    int32_t *acc_cnt;
+    double zref_acc;
 };
 auv_status launch_idw(const auv_bin_view &bins, const IdwArgs &a, hipStream_t st);
 

@@ -605,19 +605,7 @@ __global__ __launch_bounds__(kThreads) void k_row_sort(RowItem it)
     row_sort_block(it, blockIdx.x, s_h, s_k, lds);
 }
 
-// Batched kernels: block b belongs to the item i with off[i] <= b < off[i+1].
-__device__ inline int item_of(const int32_t *off, int count, int b)
-{
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= b)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
+// Batched kernels: block b belongs to item item_of(off, count, b).
 
 __global__ __launch_bounds__(kThreads) void k_row_fill_batch(const RowItem *items)
 {

@@ -629,38 +629,53 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
             bi = s_bidx[q];
             hit = s_bd2[q] == 0.0;
         }
-        const bool over = act && kcap > 0 && cnt > kcap;
-        if (act && !over) {
-            const int64_t o = (int64_t)(ta0 + la) * a.nx + tb0 + lb;
-            if (kMode & 2) {
-                if (a.nn_idx_out)
-                    a.nn_idx_out[o] = cnt > 0 ? bi : -1;
-                if (a.nn_z_out) {
-                    float bz;
-                    if constexpr (kPacked)
-                        bz = cnt > 0 ? __int_as_float(bv.rec[bi].w) : NAN;
-                    else
-                        bz = cnt > 0 ? s_bz[q] : NAN;
-                    a.nn_z_out[o] = bz;
+        if constexpr ((kMode & 4) != 0) {
+            // accumulate mode (no cap): add this tile's sums into the resident
+            // per-node accumulators, re-referenced from the tile's depth to
+            // the accumulators' depth.  One lane owns each node; the caller
+            // guarantees that no other wave updates the same node meanwhile.
+            if (act && cnt > 0) {
+                const int64_t o = (int64_t)(ta0 + la) * a.nx + tb0 + lb;
+                const float2 nd = s_nd[q];
+                const double shift = (double)zref - a.zref_acc;
+                a.acc_num[o] += (float)((double)nd.x + (double)nd.y * shift);
+                a.acc_den[o] += nd.y;
+                a.acc_cnt[o] += cnt;
+            }
+        } else {
+            const bool over = act && kcap > 0 && cnt > kcap;
+            if (act && !over) {
+                const int64_t o = (int64_t)(ta0 + la) * a.nx + tb0 + lb;
+                if (kMode & 2) {
+                    if (a.nn_idx_out)
+                        a.nn_idx_out[o] = cnt > 0 ? bi : -1;
+                    if (a.nn_z_out) {
+                        float bz;
+                        if constexpr (kPacked)
+                            bz = cnt > 0 ? __int_as_float(bv.rec[bi].w) : NAN;
+                        else
+                            bz = cnt > 0 ? s_bz[q] : NAN;
+                        a.nn_z_out[o] = bz;
+                    }
+                }
+                if constexpr (kIdw) {
+                    if (a.cnt_out)
+                        a.cnt_out[o] = cnt;
+                    // a hit (best D^2 == 0) carries a dominant weight, so the
+                    // ratio is the mean of the hits, and it beats min_pts
+                    const bool hole = cnt == 0 || (cnt < a.min_pts && !hit);
+                    const float2 nd = s_nd[q];
+                    a.z_out[o] = hole ? NAN : (float)((double)zref + (double)nd.x / (double)nd.y);
                 }
             }
-            if constexpr (kIdw) {
-                if (a.cnt_out)
-                    a.cnt_out[o] = cnt;
-                // a hit (best D^2 == 0) carries a dominant weight, so the
-                // ratio is the mean of the hits, and it beats min_pts
-                const bool hole = cnt == 0 || (cnt < a.min_pts && !hit);
-                const float2 nd = s_nd[q];
-                a.z_out[o] = hole ? NAN : (float)((double)zref + (double)nd.x / (double)nd.y);
+            unsigned long long om = __ballot(over);
+            while (om) {
+                const int l = __ffsll((long long)om) - 1;
+                om &= om - 1;
+                const int qn = q0 + l;
+                exact_node<kMode, kPmode, kPrec>(bv, a, g.X0, g.Y0, g.DXl, g.DYl, ta0 + qn / kTN,
+                                                 tb0 + qn % kTN, zref);
             }
-        }
-        unsigned long long om = __ballot(over);
-        while (om) {
-            const int l = __ffsll((long long)om) - 1;
-            om &= om - 1;
-            const int qn = q0 + l;
-            exact_node<kMode, kPmode, kPrec>(bv, a, g.X0, g.Y0, g.DXl, g.DYl, ta0 + qn / kTN,
-                                             tb0 + qn % kTN, zref);
         }
     }
 }

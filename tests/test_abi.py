@@ -127,3 +127,41 @@ def test_batch_plan_rejects_bad_items():
     it.z_out = None
     arr = (ag.auv_batch_item * 1)(it)
     assert lib.auv_batch_plan(arr, 1, None, ctypes.byref(h)) == ag.AUV_ERR_INVALID
+
+
+def _serve_desc(**kw):
+    grids = [ag.make_desc(v * 8192.0, 0.0, 2.0, 2.0, 2048, 2048) for v in range(4)]
+    return ag.session_desc(grids, **kw)
+
+
+def test_session_budget_on_host():
+    fixed, per_vehicle = ag.auv_session_budget(_serve_desc(max_request=50000, slots=8))
+    # three 4-byte planes per node of a 2048^2 grid
+    assert per_vehicle == 3 * 2048 * 2048 * 4
+    # per slot: 24 B per sounding staged plus the binning workspace of 514^2 bins
+    assert 8 * (50000 * 24 + 514 * 514 * 8) < fixed < 8 * (50000 * 200 + 514 * 514 * 20) + 2 ** 22
+    f2, _ = ag.auv_session_budget(_serve_desc(max_request=50000, slots=16))
+    assert f2 > fixed
+
+
+@pytest.mark.parametrize("kw, needle", [
+    ({"power": 2.5}, "power"),
+    ({"max_request": 0}, "max_request"),
+    ({"slots": 0}, "slots"),
+    ({"mode": 7}, "mode"),
+    ({"max_batch": 65}, "max_batch"),
+    ({"radius": 300.0}, "radius"),
+    ({"radius": 20.0}, "window"),
+])
+def test_session_desc_validation_on_host(kw, needle):
+    with pytest.raises(ag.AuvError) as e:
+        ag.auv_session_budget(_serve_desc(**kw))
+    assert needle in str(e.value)
+
+
+def test_session_rejects_capped_idw_on_host():
+    d = _serve_desc()
+    d.params.max_pts = 16
+    with pytest.raises(ag.AuvError) as e:
+        ag.auv_session_budget(d)
+    assert "max_pts" in str(e.value)
