@@ -18,7 +18,7 @@
  * Source of the method: "Towards Real-Time Interpolation for Enhanced AUV
  * Deep Sea Mapping" (Saxena).  The paper defines bilinear interpolation
  * (Sec. III-A), NaN samples as invalid candidates (Sec. III-B, III-D), holes
- * where bilinear has no value (Sec. III-D, V-B), a "nearest n valid candidate
+ * where bilinear has no value (Sec. III-D, V-D), a "nearest n valid candidate
  * neighbours" helper (Sec. III-D) and GPU-resident real-time interpolation
  * with the host only in control (Sec. IV).  The radius-limited IDW and the
  * nearest-neighbour gridding below generalise that helper; their exact

@@ -11,7 +11,7 @@
  * DESIGN.md under "Readings"):
  *   - bilinear: Sec. III-A, the four-corner weighted average;
  *   - NaN samples are invalid candidates: Sec. III-B and III-D;
- *   - holes (no fallback for bilinear): Sec. III-D and V-B (Kerguelen);
+ *   - holes (no fallback for bilinear): Sec. III-D and V-D (Kerguelen);
  *   - "nearest n valid candidate neighbours" helper: Sec. III-D, item 1,
  *     generalised to a radius-limited, optionally capped neighbour set.
  *

@@ -1,4 +1,8 @@
 // Binning of soundings into a cell hash: a stable counting sort on gfx950.
+// Two paths give the same result (bins in id order, each bin's members in
+// original index order): the row path further below, for bin domains of at
+// most 8192 rows and columns (its histograms live in LDS), and this general
+// path for larger ones:
 //
 //   k_rebase_count   FP64 rebase of each sounding onto the 2^-16 m lattice of
 //                    the grid, validity / domain test, bin id, atomic
