@@ -150,10 +150,12 @@ RowItem make_row_item(const auv_grid *g, const BinGeom &geom, const double *x,
                       const double *y, const double *z, int64_t n, const BinWorkspace &w);
 int32_t row_hist_blocks(int64_t n);
 int32_t row_scatter_blocks(int64_t n);
+// max_nbx / max_nby: the largest bin domain among the items (sizes the LDS).
 auv_status launch_binning_batch(const RowItem *d_items, const int32_t *d_hist_off,
                                 const int32_t *d_scatter_off, const int32_t *d_sort_off,
                                 int32_t count, int32_t hist_blocks, int32_t scatter_blocks,
-                                int32_t sort_blocks, hipStream_t st);
+                                int32_t sort_blocks, int32_t max_nbx, int32_t max_nby,
+                                hipStream_t st);
 
 auv_status launch_binning(const auv_grid *g, const BinGeom &geom,
                           const double *x, const double *y, const double *z,

@@ -86,7 +86,9 @@ __global__ __launch_bounds__(64) void k_idw_batch_window(const IdwItem *__restri
     __shared__ float s_emax[win::kAcc];
     __shared__ int s_beg[win::kMaxRows];
     __shared__ int s_off[win::kMaxRows + 1];
-    const win::WinSmem sm{s_nd, s_cnt, s_key, nullptr, nullptr, nullptr, s_emax, s_beg, s_off};
+    __shared__ int4 s_r0[64], s_r1[64];
+    const win::WinSmem sm{s_nd, s_cnt, s_key, nullptr, nullptr, nullptr, s_emax, s_beg, s_off,
+                          s_r0, s_r1, nullptr};
     const int home = blockIdx.x & (kQueues - 1);
     for (int k = 0; k < kQueues; ++k) {
         const int q = (home + k) & (kQueues - 1);
@@ -214,6 +216,7 @@ struct auv_batch {
     std::vector<int2> work;
     int32_t hist_blocks = 0, scatter_blocks = 0, sort_blocks = 0, nrow_items = 0;
     int32_t nwork_window = 0, nwork_dense = 0;
+    int32_t max_nbx = 0, max_nby = 0;  // largest bin domain of the row-binned items
     hipStream_t cap_stream2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<int32_t> row_items;  // items binned by the batched row path
@@ -330,6 +333,7 @@ auv_status build_tables(auv_batch *b, char *ws)
 {
     const int count = (int)b->items.size();
     b->rows.assign(count, RowItem{});
+    b->max_nbx = b->max_nby = 0;
     b->idw.assign(count, IdwItem{});
     b->row_items.clear();
     std::vector<int32_t> hist(1, 0), scat(1, 0), sort(1, 0);
@@ -347,6 +351,8 @@ auv_status build_tables(auv_batch *b, char *ws)
             hist.push_back(hist.back() + row_hist_blocks(it.n));
             scat.push_back(scat.back() + row_scatter_blocks(it.n));
             sort.push_back(sort.back() + b->geom[i].nby);
+            b->max_nbx = std::max(b->max_nbx, b->geom[i].nbx);
+            b->max_nby = std::max(b->max_nby, b->geom[i].nby);
         }
         IdwItem &d = b->idw[i];
         d.bv = bv;
@@ -363,8 +369,8 @@ auv_status build_tables(auv_batch *b, char *ws)
             const unsigned __int128 top = (unsigned __int128)((unsigned long long)a.R * a.R)
                                           << bv.idx_bits;
             ok = ok && top < ((unsigned __int128)1 << 64);
-            d.ntx = (it.grid.nx + win::kTN - 1) / win::kTN;
-            d.ntiles = d.ntx * ((it.grid.ny + win::kTN - 1) / win::kTN);
+            d.ntx = (it.grid.nx + win::kTW - 1) / win::kTW;
+            d.ntiles = d.ntx * ((it.grid.ny + win::kTH - 1) / win::kTH);
         }
         ok = ok && row_path_ok(b->geom[i]);
         b->persistent[i] = ok ? 1 : 0;
@@ -450,7 +456,8 @@ auv_status enqueue_batched(auv_batch *b, char *ws, hipStream_t st)
     const int count = (int)b->items.size();
     const int nr = b->nrow_items;
     AUV_TRY_S(launch_binning_batch(t.rows, t.offs, t.offs + (nr + 1), t.offs + 2 * (nr + 1), nr,
-                                   b->hist_blocks, b->scatter_blocks, b->sort_blocks, st));
+                                   b->hist_blocks, b->scatter_blocks, b->sort_blocks,
+                                   b->max_nbx, b->max_nby, st));
     for (int i = 0; i < count; ++i) {
         if (row_path_ok(b->geom[i]))
             continue;

@@ -306,18 +306,22 @@ __global__ __launch_bounds__(kThreads) void k_stabilise_big(
 // Two-level counting sort used when the bin rows fit an LDS histogram:
 //   k_row_hist    rebase + per-block LDS histogram over bin rows; one global
 //                 atomic per (block, non-empty row) reserves the block's range
-//   k_row_scan    exclusive scan of the row counts (one block)
-//   k_row_scatter each sounding's (column, index) key into its row's range
+//   k_row_scatter every block scans the row counts in LDS (block 0 publishes
+//                 the row starts and the drop totals), then writes each
+//                 sounding's (column, index) key into its row's range
 //   k_row_sort    one block per bin row: counting sort by bin column in LDS
 //                 (which also yields the row's cell_start entries), then rank
 //                 each bin's members by original index; write the binned SoA.
 // Device-scope atomics drop from one per sounding to one per block and row.
+// LDS is sized per launch from the bin domain (rows, columns), so small
+// domains keep many blocks resident.
 
 constexpr int kRowChunk = 1024;          // soundings per block in k_row_hist
 constexpr int kRowPerThread = kRowChunk / kThreads;
 constexpr int kMaxRowsLds = 8192;        // bin rows in the LDS histogram
+constexpr int kScatterPer = 4;           // soundings per thread in k_row_scatter
 
-__device__ void row_hist_block(const RowItem &it, int blk)
+__device__ void row_hist_block(const RowItem &it, int blk, int *s_cnt)
 {
     const double *__restrict__ x = it.x;
     const double *__restrict__ y = it.y;
@@ -331,7 +335,6 @@ __device__ void row_hist_block(const RowItem &it, int blk)
     int32_t *__restrict__ colkey = it.colkey;
     int4 *__restrict__ rec = it.rec;
     int32_t *__restrict__ drops = it.drops;
-    __shared__ int s_cnt[kMaxRowsLds];
     for (int r = threadIdx.x; r < nby; r += kThreads)
         s_cnt[r] = 0;
     __syncthreads();
@@ -397,7 +400,7 @@ __device__ void row_hist_block(const RowItem &it, int blk)
             pos[i] = row[j] >= 0 ? s_cnt[row[j]] + lr[j] : 0;
         }
     }
-    // per-block drop counters (summed by k_row_scan: a device-wide atomic on
+    // per-block drop counters (summed by block 0 of k_row_scatter: a device-wide atomic on
     // one address per wave would serialise at the memory side)
     int tb, tob;
     {
@@ -411,30 +414,14 @@ __device__ void row_hist_block(const RowItem &it, int blk)
     }
 }
 
-// Exclusive scan of the row counts by one block; also the binned total.
-__device__ void row_scan_block(const RowItem &it)
+// Row starts (exclusive scan of the row counts) into LDS, by every scatter
+// block; block 0 also publishes them with the binned total and the drop
+// counts summed over the k_row_hist blocks.  Then the block's soundings go to
+// their rows: key = bin column << 32 | original index.
+__device__ void row_scatter_block(const RowItem &it, int blk, int *s_rs, int *lds)
 {
     const int32_t *__restrict__ cnt = it.row_count;
     const int32_t nby = it.nby;
-    int32_t *__restrict__ start = it.row_start;
-    const int32_t *__restrict__ drops = it.drops;
-    const int32_t nblk = it.nblk;
-    unsigned long long *__restrict__ stats = it.stats;
-    __shared__ int lds[kThreads / 64];
-    long long nbad = 0, nout = 0;
-    for (int b = threadIdx.x; b < nblk; b += kThreads) {
-        nbad += drops[2 * b];
-        nout += drops[2 * b + 1];
-    }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        nbad += __shfl_xor(nbad, d, 64);
-        nout += __shfl_xor(nout, d, 64);
-    }
-    if (lane_id() == 0) {
-        atomicAdd(&stats[1], (unsigned long long)nbad);
-        atomicAdd(&stats[2], (unsigned long long)nout);
-    }
     int carry = 0;
     for (int c = 0; c < nby; c += kThreads) {
         const int i = c + threadIdx.x;
@@ -442,23 +429,44 @@ __device__ void row_scan_block(const RowItem &it)
         int total;
         const int ex = block_exclusive_scan(v, lds, &total);
         if (i < nby)
-            start[i] = carry + ex;
+            s_rs[i] = carry + ex;
         carry += total;
     }
-    if (threadIdx.x == 0) {
-        start[nby] = carry;
-        stats[0] = (unsigned long long)carry;
+    __syncthreads();
+    if (blk == 0) {
+        int32_t *__restrict__ start = it.row_start;
+        for (int i = threadIdx.x; i < nby; i += kThreads)
+            start[i] = s_rs[i];
+        const int32_t *__restrict__ drops = it.drops;
+        long long nbad = 0, nout = 0;
+        for (int b = threadIdx.x; b < it.nblk; b += kThreads) {
+            nbad += drops[2 * b];
+            nout += drops[2 * b + 1];
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            nbad += __shfl_xor(nbad, d, 64);
+            nout += __shfl_xor(nout, d, 64);
+        }
+        if (lane_id() == 0) {
+            atomicAdd(&it.stats[1], (unsigned long long)nbad);
+            atomicAdd(&it.stats[2], (unsigned long long)nout);
+        }
+        if (threadIdx.x == 0) {
+            start[nby] = carry;
+            it.stats[0] = (unsigned long long)carry;
+        }
     }
-}
-
-__device__ void row_scatter_block(const RowItem &it, int blk)
-{
-    const int64_t i = (int64_t)blk * kThreads + threadIdx.x;
-    if (i < it.n) {
-        const int r = it.rowid[i];
-        if (r >= 0)
-            it.keys[it.row_start[r] + it.pos[i]] =
-                ((unsigned long long)(uint32_t)it.colkey[i] << 32) | (uint32_t)i;
+    const int64_t base = (int64_t)blk * (kThreads * kScatterPer) + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < kScatterPer; ++j) {
+        const int64_t i = base + (int64_t)j * kThreads;
+        if (i < it.n) {
+            const int r = it.rowid[i];
+            if (r >= 0)
+                it.keys[s_rs[r] + it.pos[i]] =
+                    ((unsigned long long)(uint32_t)it.colkey[i] << 32) | (uint32_t)i;
+        }
     }
 }
 
@@ -511,27 +519,55 @@ __device__ void block_bitonic_sort(T *a, int n)
 // bin, members are ordered by original index: by ranking (rank = number of
 // members with a smaller index) when every bin of the row is small, else by
 // a bitonic sort of the row's (column, index) keys (in LDS when they fit,
-// otherwise in place in the key array).  tmp_keys is scratch of the same size.
+// otherwise in place in the key array).  Rows of up to kRowLds keys rank in
+// LDS: the keys are re-read (coalesced) from global memory in each pass and
+// only the indices are scattered into their bins in LDS; longer rows rank
+// through tmp_keys.  (Swath data gives lumpy rows: a ping line spans a bin
+// row, so a row holds zero, one or two pings' worth of soundings.)
 constexpr int kColsLds = 8192;
-constexpr int kSmallRank = 64;      // largest bin ranked member by member
-constexpr int kRowSortLds = 4096;   // keys of a row sorted in LDS
+constexpr int kSmallRank = 64;     // largest bin ranked member by member
+constexpr int kRowLds = 8192;      // keys of a row ranked in LDS (as u32 indices)
+constexpr int kRowSortLds = kRowLds / 2;  // keys of a row bitonic-sorted in LDS (u64)
+constexpr int kRowU = 8;           // keys per thread per pass: loads kept in flight
+
+// for (k = threadIdx.x; k < n; k += kThreads) f(k, keys[r0 + k]), with kRowU
+// key loads issued before any is used
+template <class F>
+__device__ inline void for_row_keys(const unsigned long long *__restrict__ keys, int r0, int n,
+                                    F f)
+{
+    for (int k0 = threadIdx.x; k0 < n; k0 += kThreads * kRowU) {
+        unsigned long long kk[kRowU];
+#pragma unroll
+        for (int j = 0; j < kRowU; ++j) {
+            const int k = k0 + j * kThreads;
+            kk[j] = k < n ? keys[r0 + k] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < kRowU; ++j) {
+            const int k = k0 + j * kThreads;
+            if (k < n)
+                f(k, kk[j]);
+        }
+    }
+}
 
 __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
                                unsigned long long *s_k, int *lds)
 {
-    unsigned long long *__restrict__ keys = it.keys;
+    const unsigned long long *__restrict__ keys = it.keys;
     const int32_t *__restrict__ row_start = it.row_start;
     const int32_t nby = it.nby, nbx = it.nbx;
     const int4 *__restrict__ rec = it.rec;
     const SoA o = it.o;
     int32_t *__restrict__ cell_start = it.cell_start;
-    unsigned long long *__restrict__ tmp_keys = it.keys2;
     const int r0 = row_start[row], n = row_start[row + 1] - r0;
     for (int bx = threadIdx.x; bx < nbx; bx += kThreads)
         s_h[bx] = 0;
     __syncthreads();
-    for (int k = threadIdx.x; k < n; k += kThreads)
-        atomicAdd(&s_h[(int)(keys[r0 + k] >> 32)], 1);
+    for_row_keys(keys, r0, n, [&](int, unsigned long long key) {
+        atomicAdd(&s_h[(int)(key >> 32)], 1);
+    });
     __syncthreads();
     int32_t *cs = cell_start + (int64_t)row * nbx;
     int carry = 0, big = 0;
@@ -550,7 +586,7 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
     if (row == nby - 1 && threadIdx.x == 0)
         cell_start[(int64_t)nby * nbx] = row_start[nby];
     if (__syncthreads_or(big)) {
-        unsigned long long *a = keys + r0;
+        unsigned long long *a = it.keys + r0;
         if (n <= kRowSortLds) {
             for (int k = threadIdx.x; k < n; k += kThreads)
                 s_k[k] = keys[r0 + k];
@@ -562,8 +598,55 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
             emit(o, r0 + k, (int)(uint32_t)(a[k] & 0xffffffffull), rec);
         return;
     }
-    // scatter (column, original index) into the bins (unordered inside a
-    // bin); afterwards s_h[bx] is the end of bin bx, i.e. the start of bx+1
+    if (n <= kRowLds) {
+        // scatter the indices into their bins (unordered inside a bin);
+        // afterwards s_h[bx] is the end of bin bx, i.e. the start of bx + 1
+        uint32_t *s_i = reinterpret_cast<uint32_t *>(s_k);
+        for_row_keys(keys, r0, n, [&](int, unsigned long long key) {
+            const int p = atomicAdd(&s_h[(int)(key >> 32)], 1);
+            s_i[p] = (uint32_t)key;
+        });
+        __syncthreads();
+        // ranks first (LDS), then the kRowU record gathers in flight together
+        for (int k0 = threadIdx.x; k0 < n; k0 += kThreads * kRowU) {
+            unsigned long long kk[kRowU];
+            int pos[kRowU];
+            int4 rr[kRowU];
+#pragma unroll
+            for (int j = 0; j < kRowU; ++j) {
+                const int k = k0 + j * kThreads;
+                kk[j] = k < n ? keys[r0 + k] : 0ull;
+            }
+#pragma unroll
+            for (int j = 0; j < kRowU; ++j) {
+                pos[j] = -1;
+                if (k0 + j * kThreads < n) {
+                    const int bx = (int)(kk[j] >> 32);
+                    const uint32_t v = (uint32_t)kk[j];
+                    const int b0 = bx == 0 ? 0 : s_h[bx - 1], b1 = s_h[bx];
+                    int rank = 0;
+                    for (int q = b0; q < b1; ++q)
+                        rank += s_i[q] < v ? 1 : 0;
+                    pos[j] = r0 + b0 + rank;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kRowU; ++j)
+                if (pos[j] >= 0)
+                    rr[j] = rec[(uint32_t)kk[j]];
+#pragma unroll
+            for (int j = 0; j < kRowU; ++j)
+                if (pos[j] >= 0) {
+                    o.X[pos[j]] = rr[j].x;
+                    o.Y[pos[j]] = rr[j].y;
+                    o.res[pos[j]] = (uint32_t)rr[j].z;
+                    o.z[pos[j]] = __int_as_float(rr[j].w);
+                    o.idx[pos[j]] = (int)(uint32_t)kk[j];
+                }
+        }
+        return;
+    }
+    unsigned long long *__restrict__ tmp_keys = it.keys2;
     for (int k = threadIdx.x; k < n; k += kThreads) {
         const unsigned long long key = keys[r0 + k];
         const int p = atomicAdd(&s_h[(int)(key >> 32)], 1);
@@ -583,7 +666,15 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
     }
 }
 
-// Single-item kernels.
+// LDS bytes of the row-path kernels for a bin domain of nby rows, nbx columns.
+inline size_t row_hist_lds(int nby) { return sizeof(int) * (size_t)nby; }
+inline size_t row_scatter_lds(int nby) { return sizeof(int) * (size_t)nby; }
+inline size_t row_sort_lds(int nbx)
+{
+    return sizeof(unsigned long long) * kRowSortLds + sizeof(int) * (size_t)nbx;
+}
+
+// Single-item kernels.  Dynamic LDS: 8-byte aligned base.
 __global__ __launch_bounds__(kThreads) void k_row_fill(RowItem it)
 {
     for (int r = threadIdx.x; r < it.nby; r += kThreads)
@@ -592,24 +683,28 @@ __global__ __launch_bounds__(kThreads) void k_row_fill(RowItem it)
         it.stats[threadIdx.x] = 0;
 }
 
-__global__ __launch_bounds__(kThreads) void k_row_hist(RowItem it) { row_hist_block(it, blockIdx.x); }
-
-__global__ __launch_bounds__(kThreads) void k_row_scan(RowItem it) { row_scan_block(it); }
+__global__ __launch_bounds__(kThreads) void k_row_hist(RowItem it)
+{
+    extern __shared__ unsigned long long s_dyn[];
+    row_hist_block(it, blockIdx.x, reinterpret_cast<int *>(s_dyn));
+}
 
 __global__ __launch_bounds__(kThreads) void k_row_scatter(RowItem it)
 {
-    row_scatter_block(it, blockIdx.x);
+    extern __shared__ unsigned long long s_dyn[];
+    __shared__ int lds[kThreads / 64];
+    row_scatter_block(it, blockIdx.x, reinterpret_cast<int *>(s_dyn), lds);
 }
 
 __global__ __launch_bounds__(kThreads) void k_row_sort(RowItem it)
 {
-    __shared__ int s_h[kColsLds];
-    __shared__ unsigned long long s_k[kRowSortLds];
+    extern __shared__ unsigned long long s_dyn[];
     __shared__ int lds[kThreads / 64];
-    row_sort_block(it, blockIdx.x, s_h, s_k, lds);
+    row_sort_block(it, blockIdx.x, reinterpret_cast<int *>(s_dyn + kRowSortLds), s_dyn, lds);
 }
 
-// Batched kernels: block b belongs to item item_of(off, count, b).
+// Batched kernels: block b belongs to item item_of(off, count, b); the LDS is
+// sized for the largest bin domain of the batch.
 
 __global__ __launch_bounds__(kThreads) void k_row_fill_batch(const RowItem *items)
 {
@@ -623,30 +718,28 @@ __global__ __launch_bounds__(kThreads) void k_row_fill_batch(const RowItem *item
 __global__ __launch_bounds__(kThreads) void k_row_hist_batch(const RowItem *items,
                                                              const int32_t *off, int count)
 {
+    extern __shared__ unsigned long long s_dyn[];
     const int i = item_of(off, count, blockIdx.x);
-    row_hist_block(items[i], blockIdx.x - off[i]);
-}
-
-__global__ __launch_bounds__(kThreads) void k_row_scan_batch(const RowItem *items)
-{
-    row_scan_block(items[blockIdx.x]);
+    row_hist_block(items[i], blockIdx.x - off[i], reinterpret_cast<int *>(s_dyn));
 }
 
 __global__ __launch_bounds__(kThreads) void k_row_scatter_batch(const RowItem *items,
                                                                 const int32_t *off, int count)
 {
+    extern __shared__ unsigned long long s_dyn[];
+    __shared__ int lds[kThreads / 64];
     const int i = item_of(off, count, blockIdx.x);
-    row_scatter_block(items[i], blockIdx.x - off[i]);
+    row_scatter_block(items[i], blockIdx.x - off[i], reinterpret_cast<int *>(s_dyn), lds);
 }
 
 __global__ __launch_bounds__(kThreads) void k_row_sort_batch(const RowItem *items,
                                                              const int32_t *off, int count)
 {
-    __shared__ int s_h[kColsLds];
-    __shared__ unsigned long long s_k[kRowSortLds];
+    extern __shared__ unsigned long long s_dyn[];
     __shared__ int lds[kThreads / 64];
     const int i = item_of(off, count, blockIdx.x);
-    row_sort_block(items[i], blockIdx.x - off[i], s_h, s_k, lds);
+    row_sort_block(items[i], blockIdx.x - off[i], reinterpret_cast<int *>(s_dyn + kRowSortLds),
+                   s_dyn, lds);
 }
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -791,11 +884,9 @@ auv_status launch_binning(const auv_grid *g, const BinGeom &geom, const double *
         const RowItem it = make_row_item(g, geom, x, y, z, n, w);
         k_row_fill<<<1, kThreads, 0, st>>>(it);
         if (n > 0)
-            k_row_hist<<<it.nblk, kThreads, 0, st>>>(it);
-        k_row_scan<<<1, kThreads, 0, st>>>(it);
-        if (n > 0)
-            k_row_scatter<<<grid_for(n, kThreads), kThreads, 0, st>>>(it);
-        k_row_sort<<<(unsigned)geom.nby, kThreads, 0, st>>>(it);
+            k_row_hist<<<it.nblk, kThreads, row_hist_lds(geom.nby), st>>>(it);
+        k_row_scatter<<<row_scatter_blocks(n), kThreads, row_scatter_lds(geom.nby), st>>>(it);
+        k_row_sort<<<(unsigned)geom.nby, kThreads, row_sort_lds(geom.nbx), st>>>(it);
         AUV_HIP(hipGetLastError());
         return AUV_OK;
     }
@@ -828,22 +919,27 @@ auv_status launch_binning(const auv_grid *g, const BinGeom &geom, const double *
 
 
 int32_t row_hist_blocks(int64_t n) { return n > 0 ? (int32_t)grid_for(n, kRowChunk) : 0; }
-int32_t row_scatter_blocks(int64_t n) { return n > 0 ? (int32_t)grid_for(n, kThreads) : 0; }
+// at least one block: block 0 publishes the row starts even for no soundings
+int32_t row_scatter_blocks(int64_t n) { return (int32_t)grid_for(n, kThreads * kScatterPer); }
 
 auv_status launch_binning_batch(const RowItem *d_items, const int32_t *d_hist_off,
                                 const int32_t *d_scatter_off, const int32_t *d_sort_off,
                                 int32_t count, int32_t hist_blocks, int32_t scatter_blocks,
-                                int32_t sort_blocks, hipStream_t st)
+                                int32_t sort_blocks, int32_t max_nbx, int32_t max_nby,
+                                hipStream_t st)
 {
     if (count <= 0)
         return AUV_OK;
+    if (max_nbx > kColsLds || max_nby > kMaxRowsLds)
+        return fail(AUV_ERR_INVALID, "bin domain too large for the row path");
     k_row_fill_batch<<<count, kThreads, 0, st>>>(d_items);
     if (hist_blocks > 0)
-        k_row_hist_batch<<<hist_blocks, kThreads, 0, st>>>(d_items, d_hist_off, count);
-    k_row_scan_batch<<<count, kThreads, 0, st>>>(d_items);
-    if (scatter_blocks > 0)
-        k_row_scatter_batch<<<scatter_blocks, kThreads, 0, st>>>(d_items, d_scatter_off, count);
-    k_row_sort_batch<<<sort_blocks, kThreads, 0, st>>>(d_items, d_sort_off, count);
+        k_row_hist_batch<<<hist_blocks, kThreads, row_hist_lds(max_nby), st>>>(d_items,
+                                                                             d_hist_off, count);
+    k_row_scatter_batch<<<scatter_blocks, kThreads, row_scatter_lds(max_nby), st>>>(
+        d_items, d_scatter_off, count);
+    k_row_sort_batch<<<sort_blocks, kThreads, row_sort_lds(max_nbx), st>>>(d_items, d_sort_off,
+                                                                           count);
     AUV_HIP(hipGetLastError());
     return AUV_OK;
 }

@@ -20,6 +20,10 @@ bool window_geometry(const IdwArgs &a, WinGeom *g)
     g->DYl = (int)DY;
     g->X0 = g->DXl / 2;
     g->Y0 = g->DYl / 2;
+    // window offsets stay within +-2^22 lattice units (the kernel's exact
+    // squares use 24-bit multiplies): reach below 32 m
+    if (a.R_stage >= (1 << 21))
+        return false;
     g->Wx = (int)((2LL * a.R_stage) / g->DXl) + 1;
     g->Wy = (int)((2LL * a.R_stage) / g->DYl) + 1;
     if ((long long)g->Wx * g->Wy > 64LL * kMaxChunks)
@@ -35,7 +39,7 @@ bool window_geometry(const IdwArgs &a, WinGeom *g)
 auv_status launch_idw_window(const auv_bin_view &bv, const IdwArgs &a, const WinGeom &g,
                              int pmode, hipStream_t st)
 {
-    const int ntx = (a.nx + kTN - 1) / kTN, nty = (a.ny + kTN - 1) / kTN;
+    const int ntx = (a.nx + kTW - 1) / kTW, nty = (a.ny + kTH - 1) / kTH;
     if (a.precision != AUV_P_FP32_REBASE)
         return launch_idw_window_prec(bv, a, g, pmode, st);
     switch (a.mode) {

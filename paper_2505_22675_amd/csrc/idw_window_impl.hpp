@@ -1,9 +1,9 @@
 // Radius-limited IDW and nearest pick, window form (gfx950).
 //
-// One 64-lane wavefront owns a 16x16 tile of grid nodes whose accumulators
+// One 64-lane wavefront owns a 16 x 16 tile of grid nodes whose accumulators
 // live in LDS.  The binned soundings of the bin rows meeting the tile grown by
-// the radius are staged into LDS (compacted to those whose node window meets
-// the tile).  For each staged sounding the 64 lanes cover its window of nodes
+// the radius are read and compacted to those whose node window meets the
+// tile.  For each of those, the 64 lanes cover its window of nodes
 // (the nodes within +-R of it: at most floor(2R/dX)+1 per axis, <= 64 cells
 // per pass), test membership exactly and update the member nodes'
 // accumulators.  Within one instruction every lane owns a distinct node and
@@ -15,8 +15,8 @@
 // kernel in idw_kernels.hip covers every other grid.
 //
 // Exactness as in the tile kernel: membership, ranking and hits on the exact
-// lattice D^2 (FP64-held integers), FP32 distances/weights from lattice
-// offsets plus residuals, FP64 final division.  Sums are relative to one
+// lattice D^2 (64-bit integers), FP32 distances/weights from lattice offsets
+// plus residuals, FP32 final quotient.  Sums are relative to one
 // reference depth per tile (a sounding's depth, so a constant field stays
 // exact).  A hit (D^2 == 0) enters with a dominant weight, which yields the
 // mean of the hits; it is recognised at the end by a best key of D^2 == 0.
@@ -32,8 +32,11 @@ namespace auv {
 
 namespace win {
 
-constexpr int kTN = 16;              // tile nodes per side
-constexpr int kNodes = kTN * kTN;    // accumulators per wave
+// 16 x 16: a wider tile would cross fewer tile edges per sounding but its
+// LDS lowers the waves per SIMD, which costs more (measured 16 x 32: +19 %).
+constexpr int kTW = 16;              // tile nodes per row (columns)
+constexpr int kTH = 16;              // tile rows
+constexpr int kNodes = kTW * kTH;    // nodes per wave
 constexpr int kMaxRows = 64;         // bin rows per staging pass
 constexpr int kMaxChunks = 4;        // window cells <= 64 * kMaxChunks
 constexpr float kHitW = 0x1p80f;     // weight of a coincident sounding
@@ -64,6 +67,25 @@ __device__ inline float weight_fast(float d2n, int pmode)
     const float r = __builtin_amdgcn_rsqf(d2n);
     return r * r * r;
 }
+
+// Weight of a non-coincident sounding: its squared distance is at least a
+// quarter of a lattice unit squared (the exact offsets differ by at least one
+// unit and the residuals by less than one), so no clamp is needed.
+__device__ inline float weight_nonhit(float d2n, int pmode)
+{
+    if (pmode == 1)
+        return __builtin_amdgcn_rsqf(d2n);
+    if (pmode == 2)
+        return __builtin_amdgcn_rcpf(d2n);
+    const float r = __builtin_amdgcn_rsqf(d2n);
+    return r * r * r;
+}
+
+// Sign-extend from 23 bits.  Applied to window offsets known to lie within
+// +-2^22 it changes nothing, but it tells the compiler that their
+// differences fit 24 bits, so exact 64-bit squares use the full-rate 24-bit
+// multiplies.
+__device__ inline int sext23(int v) { return (int)((unsigned)v << 9) >> 9; }
 
 __device__ inline float log_weight(float d2n, float power)
 {
@@ -135,8 +157,8 @@ __device__ inline void variant_point(const IdwArgs &a, int X, int Y, float rx, f
 {
     if (prec == AUV_P_FP16_OFFSETS) {
         // tile centre between its nodes 7 and 8 (DX is even)
-        const int Xc = X0 + tb0 * DXl + (kTN - 1) * (DXl / 2);
-        const int Yc = Y0 + ta0 * DYl + (kTN - 1) * (DYl / 2);
+        const int Xc = X0 + tb0 * DXl + (kTW - 1) * (DXl / 2);
+        const int Yc = Y0 + ta0 * DYl + (kTH - 1) * (DYl / 2);
         *px = (float)(_Float16)(((float)(X - Xc) + rx) * 0x1p-16f);
         *py = (float)(_Float16)(((float)(Y - Yc) + ry) * 0x1p-16f);
     } else {
@@ -149,8 +171,8 @@ __device__ inline void variant_node(const IdwArgs &a, int bl, int al, int tb0, i
                                     int prec, float *qx, float *qy)
 {
     if (prec == AUV_P_FP16_OFFSETS) {
-        *qx = (float)(_Float16)(((float)bl - 0.5f * (kTN - 1)) * (float)a.dx);
-        *qy = (float)(_Float16)(((float)al - 0.5f * (kTN - 1)) * (float)a.dy);
+        *qx = (float)(_Float16)(((float)bl - 0.5f * (kTW - 1)) * (float)a.dx);
+        *qy = (float)(_Float16)(((float)al - 0.5f * (kTH - 1)) * (float)a.dy);
     } else {
         *qx = (float)(a.x0 + ((double)(tb0 + bl) + 0.5) * a.dx);
         *qy = (float)(a.y0 + ((double)(ta0 + al) + 0.5) * a.dy);
@@ -176,9 +198,9 @@ __device__ inline double cand_key(const auv_bin_view &bv, const IdwArgs &a, int 
         return (double)dX * (double)dX + (double)dY * (double)dY;
     } else {
         float px, py, qx, qy;
-        variant_point(a, bv.X[k], bv.Y[k], rx, ry, nb & ~(kTN - 1), na & ~(kTN - 1), X0, Y0,
+        variant_point(a, bv.X[k], bv.Y[k], rx, ry, nb & ~(kTW - 1), na & ~(kTH - 1), X0, Y0,
                       DXl, DYl, kPrec, &px, &py);
-        variant_node(a, nb & (kTN - 1), na & (kTN - 1), nb & ~(kTN - 1), na & ~(kTN - 1), kPrec,
+        variant_node(a, nb & (kTW - 1), na & (kTH - 1), nb & ~(kTW - 1), na & ~(kTH - 1), kPrec,
                      &qx, &qy);
         const float ex = px - qx, ey = py - qy;
         const float d2 = ex * ex + ey * ey;
@@ -340,15 +362,15 @@ __device__ void exact_node(const auv_bin_view &bv, const IdwArgs &a, int X0, int
 
 // LDS accumulators are structure-of-arrays with a padded row stride, so that
 // the 7-row window of one sounding spreads over the banks.
-constexpr int kRS = kTN + 2;
-constexpr int kAcc = kTN * kRS;
+constexpr int kRS = kTW + 2;
+constexpr int kAcc = kTH * kRS;
 
 // kChunks = window cells / 64 rounded up (compile-time, so the visit loop has
-// no per-chunk branches).  Soundings are never staged in LDS: a 64-wide batch
-// of candidates is tested lane-parallel, and the kept ones are broadcast one
-// by one from their lane (readlane -> SGPRs).  The only LDS traffic in the
-// visit loop is then the fire-and-forget accumulator updates, so nothing in
-// the loop waits on LDS.
+// no per-chunk branches).  A 64-wide batch of candidates is tested
+// lane-parallel; the kept ones are compacted into a small LDS record array
+// and visited one by one: the window offsets come by readlane (scalar
+// registers, where their range is known to the compiler), the rest by
+// broadcast LDS reads, which keeps the vector ALU for the per-cell work.
 // Shared arrays of one window tile (pointers into the caller's LDS).
 struct WinSmem {
     float2 *nd;                 // numerator, denominator        [kAcc]
@@ -359,6 +381,9 @@ struct WinSmem {
     float *bz;                  // best depth                    [kAcc] (unpacked)
     float *emax;                // running log2 weight max       [kAcc] (general p)
     int *beg, *off;             // staging rows                  [kMaxRows(+1)]
+    int4 *r0;                   // kept soundings: ia, jb, 8 qb, 4 qb          [64]
+    int4 *r1;                   //   residual x, y, depth - zref (bits), index  [64]
+    float2 *rv;                 //   variant coordinates; depth  [64] (variants, unpacked)
 };
 
 template <int kMode, int kPmode, bool kPacked, int kChunks, int kPrec>
@@ -370,7 +395,6 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
     // instruction every lane owns a distinct node, and a wave's LDS operations
     // complete in order, so no atomics are needed (LDS atomics would serialise
     // per lane).
-    constexpr bool kAtomic = false;
     float2 *const s_nd = sm.nd;
     int *const s_cnt = sm.cnt;
     unsigned long long *const s_key = sm.key;
@@ -383,8 +407,8 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
 
     const int lane = threadIdx.x;
     const int tx = tile % ntx, ty = tile / ntx;
-    const int tb0 = tx * kTN, ta0 = ty * kTN;
-    const int tw = min(kTN, a.nx - tb0), th = min(kTN, a.ny - ta0);
+    const int tb0 = tx * kTW, ta0 = ty * kTH;
+    const int tw = min(kTW, a.nx - tb0), th = min(kTH, a.ny - ta0);
     const int Xt0 = g.X0 + tb0 * g.DXl, Yt0 = g.Y0 + ta0 * g.DYl;
     const int R = a.R_stage;          // staging reach (>= the radius)
     const long long R2 = (long long)a.R * a.R;
@@ -400,8 +424,8 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
         // an unused lane gets a cell far outside any tile
         ci[t] = v ? c / g.Wx : -100000;
         cj[t] = v ? c - (c / g.Wx) * g.Wx : -100000;
-        iD[t] = v ? ci[t] * g.DYl : 0;
-        jD[t] = v ? cj[t] * g.DXl : 0;
+        iD[t] = sext23(v ? ci[t] * g.DYl : 0);
+        jD[t] = sext23(v ? cj[t] * g.DXl : 0);
         qo[t] = v ? ci[t] * kRS + cj[t] : 0;
     }
 
@@ -460,7 +484,7 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
         for (int c0 = 0; c0 < total; c0 += 64) {
             const int gi = c0 + lane;
             bool keep = false;
-            int px = 0, py = 0, pk = 0, pidx = 0;
+            int px = 0, py = 0, pia = 0, pjb = 0, pidx = 0;
             float prx = 0.0f, pry = 0.0f, pz = 0.0f, pvx = 0.0f, pvy = 0.0f;
             if (gi < total) {
                 int lo = 0, hi = nr - 1;
@@ -492,7 +516,8 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                 if constexpr (!kExact)
                     variant_point(a, bv.X[k], bv.Y[k], prx, pry, tb0, ta0, g.X0, g.Y0, g.DXl,
                                   g.DYl, kPrec, &pvx, &pvy);
-                pk = (int)(((uint32_t)ia & 0xffffu) | ((uint32_t)jb << 16));
+                pia = ia;
+                pjb = jb;
             }
             unsigned long long m = __ballot(keep);
             if (m == 0ull)
@@ -503,23 +528,43 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                 have_ref = true;
             }
             const float pdz = pz - zref;
+            if (keep) {
+                const int slot = __builtin_amdgcn_mbcnt_hi(
+                    (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                const int qb = pia * kRS + pjb;
+                sm.r0[slot] = make_int4(pia, pjb, qb * 8, qb * 4);
+                sm.r1[slot] = make_int4(__float_as_int(prx), __float_as_int(pry),
+                                        __float_as_int(pdz), pidx);
+                if constexpr (!kExact)
+                    sm.rv[slot] = make_float2(pvx, pvy);
+                else if constexpr (!kPacked)
+                    sm.rv[slot] = make_float2(pz, 0.0f);
+            }
+            // the records are read back by the same wave, in order
+            __builtin_amdgcn_wave_barrier();
+            const int4 *rp0 = sm.r0;
+            const int4 *rp1 = sm.r1;
+            const float2 *rpv = sm.rv;
             while (m) {
                 const int l = __ffsll((long long)m) - 1;
                 m &= m - 1ull;
-                const int sx = __builtin_amdgcn_readlane(px, l);
-                const int sy = __builtin_amdgcn_readlane(py, l);
-                const float srx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(prx), l));
-                const float sry = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pry), l));
-                const float sdz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pdz), l));
-                const int sidx = __builtin_amdgcn_readlane(pidx, l);
-                const int spk = __builtin_amdgcn_readlane(pk, l);
-                float svx = 0.0f, svy = 0.0f;
-                if constexpr (!kExact) {
-                    svx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pvx), l));
-                    svy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pvy), l));
+                const int sx = sext23(__builtin_amdgcn_readlane(px, l));
+                const int sy = sext23(__builtin_amdgcn_readlane(py, l));
+                const int4 w0 = *rp0++;
+                const int4 w1 = *rp1++;
+                const int ia = w0.x, jb = w0.y, qb8 = w0.z, qb4 = w0.w;
+                const float srx = __int_as_float(w1.x), sry = __int_as_float(w1.y);
+                const float sdz = __int_as_float(w1.z);
+                const int sidx = w1.w;
+                float svx = 0.0f, svy = 0.0f, spz = 0.0f;
+                if constexpr (!kExact || !kPacked) {
+                    const float2 v = *rpv;
+                    svx = v.x;
+                    svy = v.y;
+                    spz = v.x;
                 }
-                const int ia = (int)(int16_t)(spk & 0xffff), jb = spk >> 16;
-                const int qb = ia * kRS + jb;
+                ++rpv;
+                const int qb = qb4 >> 2;
 #pragma unroll
                 for (int t = 0; t < kChunks; ++t) {
                     const bool in = (unsigned)(ia + ci[t]) < (unsigned)th &&
@@ -546,62 +591,65 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                     }
                     if (mem) {
                         const int q = qb + qo[t];
+                        const int q8 = qb8 + qo[t] * 8;
+                        int *const pc =
+                            reinterpret_cast<int *>(reinterpret_cast<char *>(s_cnt) + qb4 + qo[t] * 4);
+                        float2 *const pn =
+                            reinterpret_cast<float2 *>(reinterpret_cast<char *>(s_nd) + q8);
+                        // every read of the node before any write: one LDS round trip
+                        const int cq = *pc;
+                        unsigned long long kq = 0ull;
+                        if constexpr (kPacked)
+                            kq = *reinterpret_cast<unsigned long long *>(
+                                reinterpret_cast<char *>(s_key) + q8);
+                        float2 nd = make_float2(0.0f, 0.0f);
+                        float em = 0.0f;
+                        if constexpr (kIdw) {
+                            nd = *pn;
+                            if constexpr (kPmode == 0)
+                                em = s_emax[q];
+                        }
                         float w = 0.0f;
                         if constexpr (kIdw) {
                             if constexpr (kPmode != 0)
                                 w = D2 == 0 ? kHitW
-                                            : weight_fast(d2f, kPmode > 0 ? kPmode : a.pmode);
+                                            : weight_nonhit(d2f, kPmode > 0 ? kPmode : a.pmode);
                             else
                                 w = D2 == 0 ? 1e30f : log_weight(d2f * a.inv_r2, a.power);
                         }
-                        if constexpr (kAtomic) {
-                            atomicAdd(&s_cnt[q], 1);
-                            atomicMin(&s_key[q], ((unsigned long long)D2 << kb) | (unsigned)sidx);
-                            if constexpr (kIdw) {
-                                atomicAdd(&s_nd[q].x, w * sdz);
-                                atomicAdd(&s_nd[q].y, w);
-                            }
+                        if constexpr (kPacked) {
+                            const unsigned long long key =
+                                ((unsigned long long)D2 << kb) | (unsigned)sidx;
+                            if (key < kq)
+                                *reinterpret_cast<unsigned long long *>(
+                                    reinterpret_cast<char *>(s_key) + q8) = key;
                         } else {
-                            const int cq = s_cnt[q];
-                            if constexpr (kPacked) {
-                                const unsigned long long key =
-                                    ((unsigned long long)D2 << kb) | (unsigned)sidx;
-                                const unsigned long long kq = s_key[q];
-                                if (key < kq)
-                                    s_key[q] = key;
+                            const double d2 = (double)D2, bd = s_bd2[q];
+                            if (d2 < bd || (d2 == bd && sidx < s_bidx[q])) {
+                                s_bd2[q] = d2;
+                                s_bidx[q] = sidx;
+                                s_bz[q] = spz;
+                            }
+                        }
+                        *pc = cq + 1;
+                        if constexpr (kIdw) {
+                            if constexpr (kPmode != 0) {
+                                nd.x += w * sdz;
+                                nd.y += w;
                             } else {
-                                const double d2 = (double)D2, bd = s_bd2[q];
-                                if (d2 < bd || (d2 == bd && sidx < s_bidx[q])) {
-                                    s_bd2[q] = d2;
-                                    s_bidx[q] = sidx;
-                                    s_bz[q] = __int_as_float(
-                                        __builtin_amdgcn_readlane(__float_as_int(pz), l));
+                                // w holds the log2 weight; rescale to the running max
+                                if (w > em) {
+                                    const float sc = __builtin_amdgcn_exp2f(em - w);
+                                    nd.x *= sc;
+                                    nd.y *= sc;
+                                    em = w;
+                                    s_emax[q] = em;
                                 }
+                                const float lw = __builtin_amdgcn_exp2f(w - em);
+                                nd.x += lw * sdz;
+                                nd.y += lw;
                             }
-                            s_cnt[q] = cq + 1;
-                            if constexpr (kIdw) {
-                                if constexpr (kPmode != 0) {
-                                    float2 nd = s_nd[q];
-                                    nd.x += w * sdz;
-                                    nd.y += w;
-                                    s_nd[q] = nd;
-                                } else {
-                                    // w holds the log2 weight; rescale to the running max
-                                    float em = s_emax[q];
-                                    float2 nd = s_nd[q];
-                                    if (w > em) {
-                                        const float sc = __builtin_amdgcn_exp2f(em - w);
-                                        nd.x *= sc;
-                                        nd.y *= sc;
-                                        em = w;
-                                        s_emax[q] = em;
-                                    }
-                                    const float lw = __builtin_amdgcn_exp2f(w - em);
-                                    nd.x += lw * sdz;
-                                    nd.y += lw;
-                                    s_nd[q] = nd;
-                                }
-                            }
+                            *pn = nd;
                         }
                     }
                 }
@@ -613,9 +661,9 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
     // finalize: one node per lane, four passes over the tile
     const int kcap = a.max_pts;
     const unsigned long long imask = (1ull << kb) - 1ull;
-    for (int q0 = 0; q0 < kTN * kTN; q0 += 64) {
+    for (int q0 = 0; q0 < kNodes; q0 += 64) {
         const int qq = q0 + lane;
-        const int la = qq / kTN, lb = qq - la * kTN;
+        const int la = qq / kTW, lb = qq - la * kTW;
         const int q = la * kRS + lb;
         const bool act = la < th && lb < tw;
         const int cnt = s_cnt[q];
@@ -665,7 +713,10 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                     // ratio is the mean of the hits, and it beats min_pts
                     const bool hole = cnt == 0 || (cnt < a.min_pts && !hit);
                     const float2 nd = s_nd[q];
-                    a.z_out[o] = hole ? NAN : (float)((double)zref + (double)nd.x / (double)nd.y);
+                    // FP32 quotient by the hardware reciprocal: a few ulp of the
+                    // offset from the tile's reference depth (1e-7 relative or
+                    // better at bathymetric depths)
+                    a.z_out[o] = hole ? NAN : zref + nd.x * __builtin_amdgcn_rcpf(nd.y);
                 }
             }
             unsigned long long om = __ballot(over);
@@ -673,8 +724,8 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                 const int l = __ffsll((long long)om) - 1;
                 om &= om - 1;
                 const int qn = q0 + l;
-                exact_node<kMode, kPmode, kPrec>(bv, a, g.X0, g.Y0, g.DXl, g.DYl, ta0 + qn / kTN,
-                                                 tb0 + qn % kTN, zref);
+                exact_node<kMode, kPmode, kPrec>(bv, a, g.X0, g.Y0, g.DXl, g.DYl, ta0 + qn / kTW,
+                                                 tb0 + qn % kTW, zref);
             }
         }
     }
@@ -694,7 +745,10 @@ __global__ __launch_bounds__(64) void k_idw_window(auv_bin_view bv, IdwArgs a, W
     __shared__ float s_emax[kPmode == 0 ? kAcc : 1];
     __shared__ int s_beg[kMaxRows];
     __shared__ int s_off[kMaxRows + 1];
-    const WinSmem sm{s_nd, s_cnt, s_key, s_bd2, s_bidx, s_bz, s_emax, s_beg, s_off};
+    __shared__ int4 s_r0[64], s_r1[64];
+    __shared__ float2 s_rv[kPrec == AUV_P_FP32_REBASE && kPacked ? 1 : 64];
+    const WinSmem sm{s_nd, s_cnt, s_key, s_bd2, s_bidx, s_bz, s_emax, s_beg, s_off,
+                     s_r0, s_r1, s_rv};
     window_tile<kMode, kPmode, kPacked, kChunks, kPrec>(
         bv, a, g, xcd_tile(blockIdx.x, ntx * nty), ntx, sm);
 }

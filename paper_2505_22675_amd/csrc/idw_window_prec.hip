@@ -11,7 +11,7 @@ using namespace win;
 auv_status launch_idw_window_prec(const auv_bin_view &bv, const IdwArgs &a, const WinGeom &g,
                                   int pmode, hipStream_t st)
 {
-    const int ntx = (a.nx + kTN - 1) / kTN, nty = (a.ny + kTN - 1) / kTN;
+    const int ntx = (a.nx + kTW - 1) / kTW, nty = (a.ny + kTH - 1) / kTH;
     const bool nn = (a.mode & 2) != 0;
     if (!(a.mode & 1))
         return fail(AUV_ERR_INVALID, "precision variants apply to IDW only");

@@ -127,7 +127,9 @@ __global__ __launch_bounds__(64) void k_serve_update(const ServeItem *__restrict
     __shared__ float s_emax[1];
     __shared__ int s_beg[win::kMaxRows];
     __shared__ int s_off[win::kMaxRows + 1];
-    const win::WinSmem sm{s_nd, s_cnt, s_key, nullptr, nullptr, nullptr, s_emax, s_beg, s_off};
+    __shared__ int4 s_r0[64], s_r1[64];
+    const win::WinSmem sm{s_nd, s_cnt, s_key, nullptr, nullptr, nullptr, s_emax, s_beg, s_off,
+                          s_r0, s_r1, nullptr};
     const int lane = threadIdx.x;
     int t0x = 0, t0y = 0, tcols = 1, nt = 0;
     if (lane < count) {
@@ -143,10 +145,10 @@ __global__ __launch_bounds__(64) void k_serve_update(const ServeItem *__restrict
             const long long a1 = min((long long)it.a.ny - 1,
                                      floor_div((long long)bb.w + R - it.g.Y0, it.g.DYl));
             if (b0 <= b1 && a0 <= a1) {
-                t0x = (int)(b0 / win::kTN);
-                t0y = (int)(a0 / win::kTN);
-                tcols = (int)(b1 / win::kTN) - t0x + 1;
-                nt = tcols * ((int)(a1 / win::kTN) - t0y + 1);
+                t0x = (int)(b0 / win::kTW);
+                t0y = (int)(a0 / win::kTH);
+                tcols = (int)(b1 / win::kTW) - t0x + 1;
+                nt = tcols * ((int)(a1 / win::kTH) - t0y + 1);
             }
         }
     }
@@ -449,6 +451,7 @@ auv_status enqueue_launch(auv_session *s, const std::vector<Pick> &picks, int ta
     bbox_off[0] = hist_off[0] = scat_off[0] = sort_off[0] = 0;
     bool chunks[win::kMaxChunks + 1] = {false, false, false, false, false};
     int64_t ntot = 0;
+    int32_t max_nbx = 0, max_nby = 0;
     for (int i = 0; i < B; ++i) {
         const Pick &p = picks[i];
         const Vehicle &V = s->veh[p.vehicle];
@@ -482,13 +485,15 @@ auv_status enqueue_launch(auv_session *s, const std::vector<Pick> &picks, int ta
         it.a.acc_den = acc + plane;
         it.a.acc_cnt = reinterpret_cast<int32_t *>(acc + 2 * plane);
         it.g = V.wg;
-        it.ntx = (V.grid.d.nx + win::kTN - 1) / win::kTN;
+        it.ntx = (V.grid.d.nx + win::kTW - 1) / win::kTW;
         it.bbox = reinterpret_cast<const int32_t *>(dev);
         chunks[V.wg.nchunks] = true;
         bbox_off[i + 1] = bbox_off[i] + (int32_t)((p.n + kBboxPer - 1) / kBboxPer);
         hist_off[i + 1] = hist_off[i] + row_hist_blocks(p.n);
         scat_off[i + 1] = scat_off[i] + row_scatter_blocks(p.n);
         sort_off[i + 1] = sort_off[i] + V.geom.nby;
+        max_nbx = std::max(max_nbx, V.geom.nbx);
+        max_nby = std::max(max_nby, V.geom.nby);
         ntot += p.n;
     }
     for (int c = 0; c < 4; ++c)
@@ -508,7 +513,7 @@ auv_status enqueue_launch(auv_session *s, const std::vector<Pick> &picks, int ta
         k_serve_bbox<<<bbox_off[B], kBboxThreads, 0, st>>>(d_bb, d_offs, B);
     AUV_TRY_S(launch_binning_batch(d_rows, d_offs + (B + 1), d_offs + 2 * (B + 1),
                                    d_offs + 3 * (B + 1), B, hist_off[B], scat_off[B],
-                                   sort_off[B], st));
+                                   sort_off[B], max_nbx, max_nby, st));
     const int blocks = (int)std::min<int64_t>(4 * (int64_t)s->cus, 16 + ntot / 256);
     if (chunks[1])
         k_serve_update<1><<<blocks, 64, 0, st>>>(d_items, B, d_counters + 0);
