@@ -192,6 +192,18 @@ auv_status auv_resample_bilinear(const float *src, const auv_grid_desc *s,
                                  float *dst, const auv_grid_desc *d,
                                  auv_stream stream);
 
+/* Catmull-Rom bicubic resample (Sec. III-B) with the same node mapping as
+ * auv_resample_bilinear: the cubic through the source nodes at index
+ * i0 - 1 .. i0 + 2 (clamped to the grid) runs along x on four rows, then
+ * along y over the four results.  A node with a non-finite value (NaN: an
+ * invalid sample) among its 16 taps falls back to the bilinear value (the
+ * "not enough valid neighbours" fallback of Sec. III-B), which is itself NaN
+ * when one of its four corners is (a hole).
+ * Same arguments, layout and errors as auv_resample_bilinear. */
+auv_status auv_resample_bicubic(const float *src, const auv_grid_desc *s,
+                                float *dst, const auv_grid_desc *d,
+                                auv_stream stream);
+
 /* ------------------------------------------------------------ batches --
  * Many independent, uneven gridding problems ("items") run as one unit: one
  * set of batched binning launches and one persistent IDW launch per kernel

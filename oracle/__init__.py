@@ -78,8 +78,9 @@ def _load():
         lib.orc_nearest.argtypes = [P(_Grid), vp, vp, vp, i64, d, i32, vp, i64,
                                     vp, vp, i32]
         lib.orc_bilinear.argtypes = [P(_Grid), vp, P(_Grid), vp, i32]
+        lib.orc_bicubic.argtypes = [P(_Grid), vp, P(_Grid), vp, i32]
         for f in (lib.orc_bin_dims, lib.orc_bin, lib.orc_idw, lib.orc_nearest,
-                  lib.orc_bilinear):
+                  lib.orc_bilinear, lib.orc_bicubic):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -186,4 +187,17 @@ def bilinear(src_grid: Grid, src, dst_grid: Grid, nthreads: int = 0):
     _check(lib.orc_bilinear(ctypes.byref(src_grid.c()), _ptr(s),
                             ctypes.byref(dst_grid.c()), _ptr(d), nthreads),
            "orc_bilinear")
+    return d.reshape(dst_grid.ny, dst_grid.nx)
+
+
+def bicubic(src_grid: Grid, src, dst_grid: Grid, nthreads: int = 0):
+    """O5: Catmull-Rom resample with bilinear fallback; [ny, nx] float64."""
+    lib = _load()
+    s = _f64(src).reshape(-1)
+    if s.shape[0] != src_grid.nx * src_grid.ny:
+        raise ValueError("source size does not match its grid")
+    d = np.empty(dst_grid.nx * dst_grid.ny, dtype=np.float64)
+    _check(lib.orc_bicubic(ctypes.byref(src_grid.c()), _ptr(s),
+                           ctypes.byref(dst_grid.c()), _ptr(d), nthreads),
+           "orc_bicubic")
     return d.reshape(dst_grid.ny, dst_grid.nx)

@@ -507,6 +507,22 @@ static void orc_axis(double x0d, double dd, int32_t j, double x0s, double ds,
     *t = u - f;
 }
 
+/* Sec. III-A in index units at one destination node: x1 = i0, x2 = i0 + 1,
+ * y1 = j0, y2 = j0 + 1, so (x2 - x1)(y2 - y1) = 1.  NaN when a corner is. */
+static double orc_bilinear_at(const orc_grid *sg, const double *src, int32_t i0, int32_t i1,
+                              double t, int32_t j0, int32_t j1, double s)
+{
+    double q11 = src[(int64_t)j0 * sg->nx + i0];
+    double q21 = src[(int64_t)j0 * sg->nx + i1];
+    double q12 = src[(int64_t)j1 * sg->nx + i0];
+    double q22 = src[(int64_t)j1 * sg->nx + i1];
+    double x2mx = 1.0 - t, xmx1 = t, y2my = 1.0 - s, ymy1 = s;
+    double v = x2mx * y2my * q11 + xmx1 * y2my * q21 + x2mx * ymy1 * q12 + xmx1 * ymy1 * q22;
+    if (isnan(q11) || isnan(q21) || isnan(q12) || isnan(q22))
+        v = NAN; /* no fallback: a hole */
+    return v;
+}
+
 int orc_bilinear(const orc_grid *sg, const double *src, const orc_grid *dg,
                  double *dst, int32_t nthreads)
 {
@@ -523,17 +539,57 @@ int orc_bilinear(const orc_grid *sg, const double *src, const orc_grid *dg,
             int32_t i0, i1;
             double t;
             orc_axis(dg->x0, dg->dx, b, sg->x0, sg->dx, sg->nx, &i0, &i1, &t);
-            /* Sec. III-A in index units: x1 = i0, x2 = i0 + 1, y1 = j0,
-             * y2 = j0 + 1, so (x2 - x1)(y2 - y1) = 1 */
-            double q11 = src[(int64_t)j0 * sg->nx + i0];
-            double q21 = src[(int64_t)j0 * sg->nx + i1];
-            double q12 = src[(int64_t)j1 * sg->nx + i0];
-            double q22 = src[(int64_t)j1 * sg->nx + i1];
-            double x2mx = 1.0 - t, xmx1 = t, y2my = 1.0 - s, ymy1 = s;
-            double v = x2mx * y2my * q11 + xmx1 * y2my * q21 + x2mx * ymy1 * q12 +
-                       xmx1 * ymy1 * q22;
-            if (isnan(q11) || isnan(q21) || isnan(q12) || isnan(q22))
-                v = NAN; /* no fallback: a hole */
+            dst[a * dg->nx + b] = orc_bilinear_at(sg, src, i0, i1, t, j0, j1, s);
+        }
+    }
+    return ORC_OK;
+}
+
+/* Catmull-Rom cubic through four equally spaced samples, at parameter t in
+ * [0, 1] between P1 and P2 (Sec. III-B). */
+static double orc_catmull_rom(double p0, double p1, double p2, double p3, double t)
+{
+    return 0.5 * (2.0 * p1 + (-p0 + p2) * t + (2.0 * p0 - 5.0 * p1 + 4.0 * p2 - p3) * t * t +
+                  (-p0 + 3.0 * p1 - 3.0 * p2 + p3) * t * t * t);
+}
+
+static int32_t orc_clamp_index(int32_t v, int32_t n)
+{
+    return v < 0 ? 0 : (v > n - 1 ? n - 1 : v);
+}
+
+int orc_bicubic(const orc_grid *sg, const double *src, const orc_grid *dg,
+                double *dst, int32_t nthreads)
+{
+    if (!orc_grid_ok(sg) || !orc_grid_ok(dg))
+        return ORC_EINVAL;
+    if (nthreads <= 0)
+        nthreads = omp_get_max_threads();
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int64_t a = 0; a < dg->ny; ++a) {
+        int32_t j0, j1;
+        double s;
+        orc_axis(dg->y0, dg->dy, (int32_t)a, sg->y0, sg->dy, sg->ny, &j0, &j1, &s);
+        for (int32_t b = 0; b < dg->nx; ++b) {
+            int32_t i0, i1;
+            double t;
+            orc_axis(dg->x0, dg->dx, b, sg->x0, sg->dx, sg->nx, &i0, &i1, &t);
+            /* 4 x 4 taps around the cell (index clamped at the edges): first
+             * along x on each of the 4 rows, then along y over the 4 results */
+            double col[4];
+            int any_nan = 0;
+            for (int r = 0; r < 4; ++r) {
+                const double *row = src + (int64_t)orc_clamp_index(j0 - 1 + r, sg->ny) * sg->nx;
+                double p[4];
+                for (int c = 0; c < 4; ++c) {
+                    p[c] = row[orc_clamp_index(i0 - 1 + c, sg->nx)];
+                    any_nan |= !isfinite(p[c]);
+                }
+                col[r] = orc_catmull_rom(p[0], p[1], p[2], p[3], t);
+            }
+            double v = orc_catmull_rom(col[0], col[1], col[2], col[3], s);
+            if (any_nan) /* an invalid neighbour: bilinear (may be a hole) */
+                v = orc_bilinear_at(sg, src, i0, i1, t, j0, j1, s);
             dst[a * dg->nx + b] = v;
         }
     }

@@ -80,6 +80,15 @@ int orc_nearest(const orc_grid *g, const double *x, const double *y,
 int orc_bilinear(const orc_grid *src_g, const double *src, const orc_grid *dst_g,
                  double *dst, int32_t nthreads);
 
+/* O5: Catmull-Rom bicubic resample (Sec. III-B): the same source index
+ * coordinate as O3, 4 x 4 taps from index i0 - 1 .. i0 + 2 (clamped to the
+ * grid), the cubic along x on each tap row, then along y; when any tap is
+ * not finite (NaN marks an invalid value) the node falls back to O3's
+ * bilinear value (reading the fallback sentence of Sec. III-B as "not enough
+ * valid neighbours"), which may itself be a hole. */
+int orc_bicubic(const orc_grid *src_g, const double *src, const orc_grid *dst_g,
+                double *dst, int32_t nthreads);
+
 #ifdef __cplusplus
 }
 #endif

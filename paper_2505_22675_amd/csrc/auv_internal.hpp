@@ -207,5 +207,7 @@ auv_status launch_idw_window_prec(const auv_bin_view &bins, const IdwArgs &a,
 
 auv_status launch_bilinear(const float *src, const auv_grid_desc &s, float *dst,
                            const auv_grid_desc &d, hipStream_t st);
+auv_status launch_bicubic(const float *src, const auv_grid_desc &s, float *dst,
+                          const auv_grid_desc &d, hipStream_t st);
 
 }  // namespace auv

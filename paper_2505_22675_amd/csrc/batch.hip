@@ -183,7 +183,10 @@ struct Choice {
 std::vector<Choice> candidates(const auv_batch_item &it, int32_t sR)
 {
     std::vector<Choice> c;
-    for (int d = -1; d <= 1; ++d)
+    // the sparse form re-does every node over the cap exactly: hopeless once
+    // a disk holds several times the cap (timing it there costs seconds)
+    const bool sparse_ok = !dense_allowed(it) || disk_population(it) < 4.0 * it.params.max_pts;
+    for (int d = -1; d <= 1 && sparse_ok; ++d)
         if (sR + d >= 12 && sR + d <= 26)
             c.push_back({sR + d, AUV_ALGO_SPARSE});
     if (dense_allowed(it) && disk_population(it) >= 0.5 * it.params.max_pts)

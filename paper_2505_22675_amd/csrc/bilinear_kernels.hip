@@ -1,4 +1,5 @@
-// Bilinear resample of one grid onto another (Sec. III-A of the paper).
+// Bilinear (Sec. III-A) and Catmull-Rom bicubic (Sec. III-B) resampling of
+// one grid onto another.
 //
 // The source index coordinate of a node is computed in FP64 with the same
 // operations, in the same order, as its definition (no contraction), so the
@@ -7,6 +8,7 @@
 #include "auv_internal.hpp"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 
 namespace auv {
@@ -141,7 +143,166 @@ __global__ __launch_bounds__(kBilThreads) void k_bilinear(BilArgs p)
     }
 }
 
+// Catmull-Rom cubic (Sec. III-B) through p0..p3 at t in [0, 1] between p1
+// and p2, in Horner form.
+__device__ inline float catmull_rom(float p0, float p1, float p2, float p3, float t)
+{
+    const float a1 = p2 - p0;
+    const float a2 = 2.0f * p0 - 5.0f * p1 + 4.0f * p2 - p3;
+    const float a3 = 3.0f * (p1 - p2) + p3 - p0;
+    return 0.5f * (((a3 * t + a2) * t + a1) * t + 2.0f * p1);
+}
+
+constexpr int kCubStage = 6144;  // source values staged in LDS (with a one-tap halo)
+
+// Catmull-Rom resample, the same patch layout as k_bilinear.  Taps are the
+// source indices i0 - 1 .. i0 + 2 (clamped to the grid) around each node's
+// cell; the cubic runs along x on the 4 tap rows, then along y.  The cubic is
+// separable: walking down its patch, each thread keeps the horizontal cubics
+// of the 4 current tap rows at its 4 columns in registers and computes a tap
+// row's horizontal cubics only when the row enters the window, so each node
+// costs one vertical cubic.  A node with a non-finite tap (NaN propagates
+// through the cubic, so its result is not finite) takes the bilinear value of
+// its 4 inner taps, NaN when one of them is NaN: a hole.
+__global__ __launch_bounds__(kBilThreads) void k_bicubic(BilArgs p)
+{
+    __shared__ int s_i0[kBilCols];
+    __shared__ float s_t[kBilCols];
+    __shared__ int s_j0[kBilRows];
+    __shared__ float s_s[kBilRows];
+    __shared__ float s_src[kCubStage];
+    const int col0 = blockIdx.x * kBilCols;
+    const int row0 = blockIdx.y * kBilRows;
+    const int ncol = min(kBilCols, p.dnx - col0);
+    const int nrow = min(kBilRows, p.dny - row0);
+    for (int c = threadIdx.x; c < kBilCols; c += kBilThreads) {
+        const Axis a = axis_of(p.dx0, p.ddx, min(col0 + c, p.dnx - 1), p.sx0, p.sdx, p.snx);
+        s_i0[c] = a.i0;
+        s_t[c] = a.t;
+    }
+    if (threadIdx.x < kBilRows) {
+        const Axis a = axis_of(p.dy0, p.ddy, min(row0 + (int)threadIdx.x, p.dny - 1), p.sy0,
+                               p.sdy, p.sny);
+        s_j0[threadIdx.x] = a.i0;
+        s_s[threadIdx.x] = a.t;
+    }
+    __syncthreads();
+    // source rectangle of every tap of the patch, clamped to the grid (the
+    // maps are monotone)
+    const int il = max(s_i0[0] - 1, 0), ih = min(s_i0[ncol - 1] + 2, p.snx - 1);
+    const int jl = max(s_j0[0] - 1, 0), jh = min(s_j0[nrow - 1] + 2, p.sny - 1);
+    const int sw = ih - il + 1, sh = jh - jl + 1;
+    const bool staged = (long long)sw * sh <= kCubStage;
+    if (staged) {
+        for (int e = threadIdx.x; e < sw * sh; e += kBilThreads) {
+            const int r = e / sw, c = e - r * sw;
+            s_src[e] = p.src[(int64_t)(jl + r) * p.snx + il + c];
+        }
+        __syncthreads();
+    }
+    const int c = threadIdx.x * 4;
+    if (c >= ncol)
+        return;
+    // tap columns (relative to the staged rectangle, or absolute) per node
+    int tc[4][4];
+    float t[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i0 = s_i0[min(c + k, ncol - 1)];
+        t[k] = s_t[min(c + k, ncol - 1)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            tc[k][q] = min(max(i0 - 1 + q, 0), p.snx - 1) - (staged ? il : 0);
+    }
+    // horizontal cubics of source row jr at this thread's 4 columns
+    auto hrow = [&](int jr) {
+        const float *row = staged ? s_src + (jr - jl) * sw : p.src + (int64_t)jr * p.snx;
+        float4 h;
+        h.x = catmull_rom(row[tc[0][0]], row[tc[0][1]], row[tc[0][2]], row[tc[0][3]], t[0]);
+        h.y = catmull_rom(row[tc[1][0]], row[tc[1][1]], row[tc[1][2]], row[tc[1][3]], t[1]);
+        h.z = catmull_rom(row[tc[2][0]], row[tc[2][1]], row[tc[2][2]], row[tc[2][3]], t[2]);
+        h.w = catmull_rom(row[tc[3][0]], row[tc[3][1]], row[tc[3][2]], row[tc[3][3]], t[3]);
+        return h;
+    };
+    auto clampr = [&](int j) { return min(max(j, 0), p.sny - 1); };
+    float4 h0 = make_float4(0.f, 0.f, 0.f, 0.f), h1 = h0, h2 = h0, h3 = h0;
+    int cur = INT_MIN;  // j0 of the rows held in h0..h3 (block-uniform)
+    const bool vec = c + 4 <= ncol && (p.dnx & 3) == 0 &&
+                     (reinterpret_cast<uintptr_t>(p.dst) & 15) == 0;
+    for (int r = 0; r < nrow; ++r) {
+        const float s = s_s[r];
+        const int j0 = s_j0[r];
+        if (j0 != cur) {
+            if (j0 == cur + 1) {
+                h0 = h1;
+                h1 = h2;
+                h2 = h3;
+                h3 = hrow(clampr(j0 + 2));
+            } else {
+                h0 = hrow(clampr(j0 - 1));
+                h1 = hrow(clampr(j0));
+                h2 = hrow(clampr(j0 + 1));
+                h3 = hrow(clampr(j0 + 2));
+            }
+            cur = j0;
+        }
+        float v[4];
+        v[0] = catmull_rom(h0.x, h1.x, h2.x, h3.x, s);
+        v[1] = catmull_rom(h0.y, h1.y, h2.y, h3.y, s);
+        v[2] = catmull_rom(h0.z, h1.z, h2.z, h3.z, s);
+        v[3] = catmull_rom(h0.w, h1.w, h2.w, h3.w, s);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!isfinite(v[k])) {
+                // bilinear on the inner taps (the corners of the node's cell)
+                const int ja = clampr(j0), jb = clampr(j0 + 1);
+                const float *r1 = staged ? s_src + (ja - jl) * sw : p.src + (int64_t)ja * p.snx;
+                const float *r2 = staged ? s_src + (jb - jl) * sw : p.src + (int64_t)jb * p.snx;
+                const float q00 = r1[tc[k][1]], q10 = r1[tc[k][2]];
+                const float q01 = r2[tc[k][1]], q11 = r2[tc[k][2]];
+                const float top = q00 + t[k] * (q10 - q00);
+                const float bot = q01 + t[k] * (q11 - q01);
+                v[k] = top + s * (bot - top);
+            }
+        }
+        float *outp = p.dst + (int64_t)(row0 + r) * p.dnx + col0 + c;
+        if (vec) {
+            typedef float f4v __attribute__((ext_vector_type(4)));
+            const f4v vv = {v[0], v[1], v[2], v[3]};
+            __builtin_nontemporal_store(vv, reinterpret_cast<f4v *>(outp));
+        } else {
+            for (int k = 0; k < 4 && c + k < ncol; ++k)
+                outp[k] = v[k];
+        }
+    }
+}
+
 }  // namespace
+
+auv_status launch_bicubic(const float *src, const auv_grid_desc &s, float *dst,
+                          const auv_grid_desc &d, hipStream_t st)
+{
+    BilArgs p;
+    p.src = src;
+    p.dst = dst;
+    p.sx0 = s.x0;
+    p.sy0 = s.y0;
+    p.sdx = s.dx;
+    p.sdy = s.dy;
+    p.dx0 = d.x0;
+    p.dy0 = d.y0;
+    p.ddx = d.dx;
+    p.ddy = d.dy;
+    p.snx = s.nx;
+    p.sny = s.ny;
+    p.dnx = d.nx;
+    p.dny = d.ny;
+    const dim3 grid((unsigned)((d.nx + kBilCols - 1) / kBilCols),
+                    (unsigned)((d.ny + kBilRows - 1) / kBilRows));
+    k_bicubic<<<grid, kBilThreads, 0, st>>>(p);
+    AUV_HIP(hipGetLastError());
+    return AUV_OK;
+}
 
 auv_status launch_bilinear(const float *src, const auv_grid_desc &s, float *dst,
                            const auv_grid_desc &d, hipStream_t st)

@@ -290,6 +290,63 @@ def test_bilinear_cfg2_upsample(ag, orc, cfg2_run):
             assert np.max(np.abs(o[ok] - ref[ok]) / np.abs(ref[ok])) <= REL
 
 
+# ---------------------------------------------------------------- bicubic --
+
+@pytest.mark.parametrize("src_shape,dst_shape,nan_frac", [
+    ((64, 64), (128, 128), 0.0), ((97, 45), (194, 90), 0.02),
+    ((50, 70), (33, 101), 0.05), ((1, 7), (3, 15), 0.0), ((2, 3), (5, 9), 0.0),
+    ((33, 33), (33, 33), 0.1), ((300, 1100), (600, 2200), 0.01)])
+def test_bicubic_parity(ag, orc, src_shape, dst_shape, nan_frac):
+    sh, sw = src_shape
+    dh, dw = dst_shape
+    rng = np.random.default_rng(sh * 1000 + dw + 7)
+    v = (-5000.0 + rng.normal(0, 400.0, (sh, sw))).astype(np.float32)
+    if nan_frac:
+        v[rng.random((sh, sw)) < nan_frac] = np.nan
+    from gen import GridSpec
+    sg = GridSpec(1000.0, 2000.0, 2.0, 3.0, sw, sh)
+    dg = GridSpec(1000.0, 2000.0, 2.0 * sw / dw, 3.0 * sh / dh, dw, dh)
+    src = torch.from_numpy(v).cuda()
+    dst = torch.empty((dh, dw), dtype=torch.float32, device="cuda")
+    ag.auv_resample_bicubic(src, sg, dst, dg)
+    torch.cuda.synchronize()
+    ref = orc.bicubic(_ogrid(orc, sg), v.astype(np.float64), _ogrid(orc, dg))
+    out = dst.cpu().numpy().astype(np.float64)
+    assert np.array_equal(np.isnan(out), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    assert np.max(np.abs(out[ok] - ref[ok]) / np.abs(ref[ok])) <= REL
+
+
+def test_bicubic_cfg2_upsample(ag, orc, cfg2_run):
+    """2x Catmull-Rom resample of the full cfg2 IDW grid (holes included) to
+    8192^2 at 1 m, sampled rows against the oracle on a band of source rows
+    that holds every tap of the row."""
+    s, res, grid, bins = cfg2_run
+    from gen import GridSpec
+    sg = s.grid
+    dg = GridSpec(0.0, 0.0, 1.0, 1.0, 8192, 8192)
+    src = torch.from_numpy(res["z"]).cuda()
+    dst = torch.empty((8192, 8192), dtype=torch.float32, device="cuda")
+    ag.auv_resample_bicubic(src, sg, dst, dg)
+    torch.cuda.synchronize()
+    out = dst.cpu().numpy()
+    nan_fallbacks = 0
+    for r in [0, 1, 2, 3, 4095, 4096, 8189, 8190, 8191, 1234, 7777, 5000]:
+        band_lo = max(0, r // 2 - 3)
+        band_hi = min(4096, r // 2 + 4)
+        sub = GridSpec(sg.x0, sg.y0 + band_lo * sg.dy, sg.dx, sg.dy, sg.nx, band_hi - band_lo)
+        drow = GridSpec(0.0, float(r), 1.0, 1.0, 8192, 1)
+        ref = orc.bicubic(_ogrid(orc, sub), res["z"][band_lo:band_hi].astype(np.float64),
+                          _ogrid(orc, drow))[0]
+        o = out[r].astype(np.float64)
+        assert np.array_equal(np.isnan(o), np.isnan(ref)), f"row {r}"
+        ok = ~np.isnan(ref)
+        nan_fallbacks += int(np.isnan(res["z"][band_lo:band_hi]).any())
+        if ok.any():
+            assert np.max(np.abs(o[ok] - ref[ok]) / np.abs(ref[ok])) <= REL, f"row {r}"
+    assert nan_fallbacks > 0
+
+
 # ------------------------------------------------------- dispatch branches --
 
 @pytest.mark.parametrize("dx,radius,kcap", [
