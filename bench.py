@@ -35,17 +35,23 @@ def host_threads() -> int:
     return len(os.sched_getaffinity(0))
 
 
-def kernel_source_digest() -> str:
-    """Digest of the HIP sources, to tell whether a committed counter profile
-    still describes the kernels being timed."""
+# Sources that define each profiled kernel (its code and its argument structs).
+KERNEL_SOURCES = {
+    "k_idw_window": ["idw_window_impl.hpp", "idw_window.hip", "auv_internal.hpp"],
+    "k_bilinear": ["bilinear_kernels.hip", "auv_internal.hpp"],
+}
+
+
+def kernel_source_digest(kernel: str) -> str:
+    """Digest of the HIP sources of `kernel`, to tell whether a committed counter
+    profile still describes the kernel being timed."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2505_22675_amd", "csrc")
-    for fn in sorted(os.listdir(csrc)):
-        if fn.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, fn), "rb") as f:
-                h.update(fn.encode())
-                h.update(f.read())
+    for fn in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(csrc, fn), "rb") as f:
+            h.update(fn.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -57,17 +63,14 @@ def traffic_from_profile(kernel: str):
     if not os.path.exists(path):
         return None
     rec = {}
-    digest = None
     with open(path) as f:
         for line in f:
-            if line.startswith("source_digest:"):
-                digest = line.split(":", 1)[1].strip()
             if line.startswith("traffic_bytes "):
-                _, name, val = line.split()
-                rec[name] = int(val)
-    if digest != kernel_source_digest():
+                _, name, val, digest = line.split()
+                rec[name] = (int(val), digest)
+    if kernel not in rec or rec[kernel][1] != kernel_source_digest(kernel):
         return None
-    return rec.get(kernel)
+    return rec[kernel][0]
 
 
 def cpu_baseline(s, up_desc, nodes):

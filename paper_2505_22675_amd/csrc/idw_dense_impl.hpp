@@ -64,7 +64,7 @@ __device__ void dense_tile(const auv_bin_view &bv, const IdwArgs &a, int tile, i
                            int pmode)
 {
     constexpr bool kIdw = (kMode & 1) != 0;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const int tx = tile % ntx, ty = tile / ntx;
     const int b = tx * kDT + (lane % kDT), an = ty * kDT + (lane / kDT);
     const bool active = b < a.nx && an < a.ny;

@@ -136,7 +136,7 @@ struct Seg {
 template <class F>
 __device__ inline void for_each_candidate(const auv_bin_view &bv, const Seg &sg, F &&f)
 {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;  // lane within the wave (blocks may hold several)
     for (int r = 0; r < sg.nrows; ++r) {
         const int id0 = (sg.by_lo + r) * bv.nbx + sg.bx_lo;
         const int s = bv.cell_start[id0], e = bv.cell_start[id0 + sg.nbx_row];
@@ -338,7 +338,7 @@ __device__ void exact_node(const auv_bin_view &bv, const IdwArgs &a, int X0, int
         num = wave_sum(num);
         den = wave_sum(den);
     }
-    if (threadIdx.x == 0) {
+    if ((threadIdx.x & 63) == 0) {
         if (kMode & 2) {
             if (a.nn_idx_out)
                 a.nn_idx_out[o] = bidx;
@@ -386,11 +386,19 @@ struct WinSmem {
     float2 *rv;                 //   variant coordinates; depth  [64] (variants, unpacked)
 };
 
+// part / nparts: the wave takes every nparts-th 64-wide chunk of the tile's
+// candidates, starting at chunk `part` (several waves can share one tile).
+// In accumulate mode with nparts > 1 the wave leaves its partial sums in LDS
+// and its reference depth in *zref_out; the caller combines the parts.
 template <int kMode, int kPmode, bool kPacked, int kChunks, int kPrec>
 __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinGeom &g,
-                            int tile, int ntx, const WinSmem &sm)
+                            int tile, int ntx, const WinSmem &sm, int part = 0,
+                            int nparts = 1, float *zref_out = nullptr)
 {
     constexpr bool kIdw = (kMode & 1) != 0;
+    // the nearest key serves the nearest outputs, hits and the cap; the
+    // accumulate mode (no cap) recognises hits by their weight instead
+    constexpr bool kKey = kPacked && (kMode & 4) == 0;
     // Accumulators are updated by plain LDS read-modify-write: within one
     // instruction every lane owns a distinct node, and a wave's LDS operations
     // complete in order, so no atomics are needed (LDS atomics would serialise
@@ -405,7 +413,7 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
     int *const s_beg = sm.beg;
     int *const s_off = sm.off;
 
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;  // lane within the wave (blocks may hold several)
     const int tx = tile % ntx, ty = tile / ntx;
     const int tb0 = tx * kTW, ta0 = ty * kTH;
     const int tw = min(kTW, a.nx - tb0), th = min(kTH, a.ny - ta0);
@@ -434,7 +442,8 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
         s_nd[q] = make_float2(0.0f, 0.0f);
         s_cnt[q] = 0;
         if constexpr (kPacked) {
-            s_key[q] = ~0ull;
+            if constexpr (kKey)
+                s_key[q] = ~0ull;
         } else {
             s_bd2[q] = 1e300;
             s_bidx[q] = INT_MAX;
@@ -481,7 +490,7 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
         if (lane == 0)
             s_off[nr] = total;
         __syncthreads();
-        for (int c0 = 0; c0 < total; c0 += 64) {
+        for (int c0 = part * 64; c0 < total; c0 += nparts * 64) {
             const int gi = c0 + lane;
             bool keep = false;
             int px = 0, py = 0, pia = 0, pjb = 0, pidx = 0;
@@ -599,7 +608,7 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                         // every read of the node before any write: one LDS round trip
                         const int cq = *pc;
                         unsigned long long kq = 0ull;
-                        if constexpr (kPacked)
+                        if constexpr (kKey)
                             kq = *reinterpret_cast<unsigned long long *>(
                                 reinterpret_cast<char *>(s_key) + q8);
                         float2 nd = make_float2(0.0f, 0.0f);
@@ -617,13 +626,13 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                             else
                                 w = D2 == 0 ? 1e30f : log_weight(d2f * a.inv_r2, a.power);
                         }
-                        if constexpr (kPacked) {
+                        if constexpr (kKey) {
                             const unsigned long long key =
                                 ((unsigned long long)D2 << kb) | (unsigned)sidx;
                             if (key < kq)
                                 *reinterpret_cast<unsigned long long *>(
                                     reinterpret_cast<char *>(s_key) + q8) = key;
-                        } else {
+                        } else if constexpr (!kPacked) {
                             const double d2 = (double)D2, bd = s_bd2[q];
                             if (d2 < bd || (d2 == bd && sidx < s_bidx[q])) {
                                 s_bd2[q] = d2;
@@ -657,6 +666,12 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
         }
     }
     __syncthreads();
+    if constexpr ((kMode & 4) != 0) {
+        if (nparts > 1) {
+            *zref_out = zref;  // partial sums stay in LDS for the caller
+            return;
+        }
+    }
 
     // finalize: one node per lane, four passes over the tile
     const int kcap = a.max_pts;
@@ -669,10 +684,13 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
         const int cnt = s_cnt[q];
         int bi;
         bool hit;
-        if constexpr (kPacked) {
+        if constexpr (kKey) {
             const unsigned long long key = s_key[q];
             bi = (int)(key & imask);
             hit = (key >> kb) == 0ull;
+        } else if constexpr (kPacked) {
+            bi = 0;
+            hit = false;
         } else {
             bi = s_bidx[q];
             hit = s_bd2[q] == 0.0;

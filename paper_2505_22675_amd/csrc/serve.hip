@@ -8,9 +8,9 @@
 //   batched row binning (the kernels behind auv_bin_points)
 //   k_serve_update<c>   persistent: (request, node tile) work over the tiles
 //                       within the radius of each request's bounding box;
-//                       the window-form gather accumulates the tile in LDS,
-//                       then each node's resident sums get one
-//                       read-modify-write
+//                       the window-form gather accumulates the tile in LDS
+//                       (four waves per tile, combined in fixed order), then
+//                       each node's resident sums get one read-modify-write
 //   an event, which the worker thread observes to complete the tickets.
 // A vehicle has at most one request per launch and launches run in stream
 // order, so a vehicle's sums see its requests in submission order and no two
@@ -114,23 +114,32 @@ __device__ inline long long floor_div(long long a, long long b)
     return (a % b != 0 && (a < 0) != (b < 0)) ? q - 1 : q;
 }
 
-// Persistent update over (request, tile) work.  Lane i of every wave holds
-// request i's tile rectangle (count <= 64), a wave-wide prefix turns the
-// pulled work index into (request, tile).
+// Persistent update over (request, tile) work, one tile per block of
+// kServeParts waves.  A request's soundings are dense, so one wave per tile
+// would run hundreds of window visits in series: the waves of the block take
+// interleaved chunks of the tile's candidates into their own LDS sums, which
+// are then combined in wave order (so the result does not depend on timing)
+// and added to the resident sums with one read-modify-write per node.  Lane i
+// of every wave holds request i's tile rectangle (count <= 64); a wave-wide
+// prefix turns the pulled work index into (request, tile).
+constexpr int kServeParts = 4;
+static_assert(win::kNodes == 64 * kServeParts, "one node per thread when combining");
+
 template <int kChunks>
-__global__ __launch_bounds__(64) void k_serve_update(const ServeItem *__restrict__ items, int count,
-                                                     int32_t *__restrict__ counter)
+__global__ __launch_bounds__(64 * kServeParts) void k_serve_update(
+    const ServeItem *__restrict__ items, int count, int32_t *__restrict__ counter)
 {
-    __shared__ float2 s_nd[win::kAcc];
-    __shared__ int s_cnt[win::kAcc];
-    __shared__ unsigned long long s_key[win::kAcc];
+    __shared__ float2 s_nd[kServeParts][win::kAcc];
+    __shared__ int s_cnt[kServeParts][win::kAcc];
     __shared__ float s_emax[1];
-    __shared__ int s_beg[win::kMaxRows];
-    __shared__ int s_off[win::kMaxRows + 1];
-    __shared__ int4 s_r0[64], s_r1[64];
-    const win::WinSmem sm{s_nd, s_cnt, s_key, nullptr, nullptr, nullptr, s_emax, s_beg, s_off,
-                          s_r0, s_r1, nullptr};
-    const int lane = threadIdx.x;
+    __shared__ int s_beg[kServeParts][win::kMaxRows];
+    __shared__ int s_off[kServeParts][win::kMaxRows + 1];
+    __shared__ int4 s_r0[kServeParts][64], s_r1[kServeParts][64];
+    __shared__ float s_zref[kServeParts];
+    __shared__ int s_task;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const win::WinSmem sm{s_nd[wave], s_cnt[wave], nullptr, nullptr, nullptr, nullptr, s_emax,
+                          s_beg[wave], s_off[wave], s_r0[wave], s_r1[wave], nullptr};
     int t0x = 0, t0y = 0, tcols = 1, nt = 0;
     if (lane < count) {
         const ServeItem &it = items[lane];
@@ -162,10 +171,11 @@ __global__ __launch_bounds__(64) void k_serve_update(const ServeItem *__restrict
     const int total = __shfl(incl, 63, 64);
     const int excl = incl - nt;
     for (;;) {
-        int t = 0;
-        if (lane == 0)
-            t = atomicAdd(counter, 1);
-        t = __builtin_amdgcn_readfirstlane(t);
+        if (threadIdx.x == 0)
+            s_task = atomicAdd(counter, 1);
+        __syncthreads();
+        const int t = s_task;
+        __syncthreads();  // every wave has its task before s_task is rewritten
         if (t >= total)
             break;
         const int i = __ffsll((long long)__ballot(incl > t)) - 1;
@@ -174,8 +184,38 @@ __global__ __launch_bounds__(64) void k_serve_update(const ServeItem *__restrict
         const int tx = __builtin_amdgcn_readlane(t0x, i) + loc % c;
         const int ty = __builtin_amdgcn_readlane(t0y, i) + loc / c;
         const ServeItem &it = items[i];
-        win::window_tile<5, -1, true, kChunks, AUV_P_FP32_REBASE>(it.bv, it.a, it.g,
-                                                                  ty * it.ntx + tx, it.ntx, sm);
+        float zr = 0.0f;
+        win::window_tile<5, -1, true, kChunks, AUV_P_FP32_REBASE>(
+            it.bv, it.a, it.g, ty * it.ntx + tx, it.ntx, sm, wave, kServeParts, &zr);
+        if (lane == 0)
+            s_zref[wave] = zr;
+        __syncthreads();
+        // combine the parts in wave order: one node per thread
+        const int tb0 = tx * win::kTW, ta0 = ty * win::kTH;
+        const int la = threadIdx.x / win::kTW, lb = threadIdx.x - la * win::kTW;
+        const int q = la * win::kRS + lb;
+        if (la < min(win::kTH, it.a.ny - ta0) && lb < min(win::kTW, it.a.nx - tb0)) {
+            double num = 0.0;
+            float den = 0.0f;
+            int cnt = 0;
+#pragma unroll
+            for (int w = 0; w < kServeParts; ++w) {
+                const int cw = s_cnt[w][q];
+                if (cw > 0) {
+                    const float2 nd = s_nd[w][q];
+                    num += (double)nd.x + (double)nd.y * ((double)s_zref[w] - it.a.zref_acc);
+                    den += nd.y;
+                    cnt += cw;
+                }
+            }
+            if (cnt > 0) {
+                const int64_t o = (int64_t)(ta0 + la) * it.a.nx + tb0 + lb;
+                it.a.acc_num[o] += (float)num;
+                it.a.acc_den[o] += den;
+                it.a.acc_cnt[o] += cnt;
+            }
+        }
+        __syncthreads();  // the LDS is reused by the next tile
     }
 }
 
@@ -514,15 +554,16 @@ auv_status enqueue_launch(auv_session *s, const std::vector<Pick> &picks, int ta
     AUV_TRY_S(launch_binning_batch(d_rows, d_offs + (B + 1), d_offs + 2 * (B + 1),
                                    d_offs + 3 * (B + 1), B, hist_off[B], scat_off[B],
                                    sort_off[B], max_nbx, max_nby, st));
-    const int blocks = (int)std::min<int64_t>(4 * (int64_t)s->cus, 16 + ntot / 256);
+    const int blocks = (int)std::min<int64_t>(2 * (int64_t)s->cus, 16 + ntot / 256);
+    const int threads = 64 * kServeParts;
     if (chunks[1])
-        k_serve_update<1><<<blocks, 64, 0, st>>>(d_items, B, d_counters + 0);
+        k_serve_update<1><<<blocks, threads, 0, st>>>(d_items, B, d_counters + 0);
     if (chunks[2])
-        k_serve_update<2><<<blocks, 64, 0, st>>>(d_items, B, d_counters + 1);
+        k_serve_update<2><<<blocks, threads, 0, st>>>(d_items, B, d_counters + 1);
     if (chunks[3])
-        k_serve_update<3><<<blocks, 64, 0, st>>>(d_items, B, d_counters + 2);
+        k_serve_update<3><<<blocks, threads, 0, st>>>(d_items, B, d_counters + 2);
     if (chunks[4])
-        k_serve_update<4><<<blocks, 64, 0, st>>>(d_items, B, d_counters + 3);
+        k_serve_update<4><<<blocks, threads, 0, st>>>(d_items, B, d_counters + 3);
     AUV_HIP(hipGetLastError());
     AUV_HIP(hipEventRecord(ev, st));
     return AUV_OK;
