@@ -61,13 +61,15 @@ __device__ inline void run_window(const IdwItem &it, int tile, const win::WinSme
                                                                   it.ntx, sm);
 }
 
-// Pull the next (item, tile) from queue q; -1 when the queue is drained.  One
-// atomic per tile, issued by lane 0 and broadcast (wave-uniform result).
-__device__ inline int pull(int32_t *qhead, int q, int len)
+// Grab the next `grab` work entries of queue q: returns the first (or -1 when
+// the queue is drained).  One atomic per grab, issued by lane 0 and broadcast
+// (wave-uniform).  Grabbing several tiles at once matters: every wave pulls
+// from a few shared counters, and same-address device atomics serialise.
+__device__ inline int pull(int32_t *qhead, int q, int len, int grab)
 {
     int t = 0;
     if (threadIdx.x == 0)
-        t = atomicAdd(&qhead[q], 1);
+        t = atomicAdd(&qhead[q], grab);
     t = __builtin_amdgcn_readfirstlane(t);
     return t < len ? t : -1;
 }
@@ -78,6 +80,7 @@ __device__ inline int pull(int32_t *qhead, int q, int len)
 __global__ __launch_bounds__(64) void k_idw_batch_window(const IdwItem *__restrict__ items,
                                                          const int2 *__restrict__ work,
                                                          const int32_t *__restrict__ qoff,
+                                                         const int32_t *__restrict__ qgrab,
                                                          int32_t *__restrict__ qhead)
 {
     __shared__ float2 s_nd[win::kAcc];
@@ -92,20 +95,22 @@ __global__ __launch_bounds__(64) void k_idw_batch_window(const IdwItem *__restri
     const int home = blockIdx.x & (kQueues - 1);
     for (int k = 0; k < kQueues; ++k) {
         const int q = (home + k) & (kQueues - 1);
-        const int len = qoff[q + 1] - qoff[q];
-        for (int t = pull(qhead, q, len); t >= 0; t = pull(qhead, q, len)) {
-            // wave-uniform work entry: the item descriptor is then read with
-            // scalar loads into SGPRs instead of occupying vector registers
-            const int2 wv = work[qoff[q] + t];
-            const int2 w = make_int2(__builtin_amdgcn_readfirstlane(wv.x),
-                                     __builtin_amdgcn_readfirstlane(wv.y));
-            const IdwItem &it = items[w.x];
-            // integer powers share one variant (the power is a runtime
-            // value there); a general power needs the rescaling variant
-            if (it.pmode != 0)
-                run_window<-1, 1>(it, w.y, sm);
-            else
-                run_window<0, 1>(it, w.y, sm);
+        const int len = qoff[q + 1] - qoff[q], grab = qgrab[q];
+        for (int t0 = pull(qhead, q, len, grab); t0 >= 0; t0 = pull(qhead, q, len, grab)) {
+            for (int t = t0; t < min(t0 + grab, len); ++t) {
+                // wave-uniform work entry: the item descriptor is then read
+                // with scalar loads into SGPRs instead of vector registers
+                const int2 wv = work[qoff[q] + t];
+                const int2 w = make_int2(__builtin_amdgcn_readfirstlane(wv.x),
+                                         __builtin_amdgcn_readfirstlane(wv.y));
+                const IdwItem &it = items[w.x];
+                // integer powers share one variant (the power is a runtime
+                // value there); a general power needs the rescaling variant
+                if (it.pmode != 0)
+                    run_window<-1, 1>(it, w.y, sm);
+                else
+                    run_window<0, 1>(it, w.y, sm);
+            }
         }
     }
 }
@@ -113,20 +118,22 @@ __global__ __launch_bounds__(64) void k_idw_batch_window(const IdwItem *__restri
 __global__ __launch_bounds__(64) void k_idw_batch_dense(const IdwItem *__restrict__ items,
                                                         const int2 *__restrict__ work,
                                                         const int32_t *__restrict__ qoff,
+                                                        const int32_t *__restrict__ qgrab,
                                                         int32_t *__restrict__ qhead)
 {
     const int home = blockIdx.x & (kQueues - 1);
     for (int k = 0; k < kQueues; ++k) {
         const int q = (home + k) & (kQueues - 1);
-        const int len = qoff[q + 1] - qoff[q];
-        for (int t = pull(qhead, q, len); t >= 0; t = pull(qhead, q, len)) {
-            // wave-uniform work entry: the item descriptor is then read with
-            // scalar loads into SGPRs instead of occupying vector registers
-            const int2 wv = work[qoff[q] + t];
-            const int2 w = make_int2(__builtin_amdgcn_readfirstlane(wv.x),
-                                     __builtin_amdgcn_readfirstlane(wv.y));
-            const IdwItem &it = items[w.x];
-            dense::dense_tile<3, kBatchDenseK>(it.bv, it.a, w.y, it.ntx, it.pmode);
+        const int len = qoff[q + 1] - qoff[q], grab = qgrab[q];
+        for (int t0 = pull(qhead, q, len, grab); t0 >= 0; t0 = pull(qhead, q, len, grab)) {
+            for (int t = t0; t < min(t0 + grab, len); ++t) {
+                // wave-uniform work entry (scalar loads of the descriptor)
+                const int2 wv = work[qoff[q] + t];
+                const int2 w = make_int2(__builtin_amdgcn_readfirstlane(wv.x),
+                                         __builtin_amdgcn_readfirstlane(wv.y));
+                const IdwItem &it = items[w.x];
+                dense::dense_tile<3, kBatchDenseK>(it.bv, it.a, w.y, it.ntx, it.pmode);
+            }
         }
     }
 }
@@ -219,6 +226,7 @@ struct auv_batch {
     std::vector<int2> work;
     int32_t hist_blocks = 0, scatter_blocks = 0, sort_blocks = 0, nrow_items = 0;
     int32_t nwork_window = 0, nwork_dense = 0;
+    int32_t blocks_window = 0, blocks_dense = 0;  // persistent grid sizes
     int32_t max_nbx = 0, max_nby = 0;  // largest bin domain of the row-binned items
     hipStream_t cap_stream2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -410,11 +418,26 @@ auv_status build_tables(auv_batch *b, char *ws)
     }
     b->nwork_window = qoff[kQueues];
     b->nwork_dense = qoff[2 * kQueues] - qoff[kQueues];
+    // tiles per grab: about 8 grabs per wave from its home queue
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    b->blocks_window = std::max(1, std::min(b->nwork_window, cus * 16));
+    b->blocks_dense = std::max(1, std::min(b->nwork_dense, cus * 8));
+    std::vector<int32_t> grab(2 * kQueues, 1);
+    for (int form = 0; form < 2; ++form) {
+        const int per_queue = std::max(1, (form ? b->blocks_dense : b->blocks_window) / kQueues);
+        for (int k = 0; k < kQueues; ++k) {
+            const int len = qoff[form * kQueues + k + 1] - qoff[form * kQueues + k];
+            grab[form * kQueues + k] = std::max(1, std::min(16, len / (8 * per_queue)));
+        }
+    }
     b->offs.clear();
     b->offs.insert(b->offs.end(), hist.begin(), hist.end());
     b->offs.insert(b->offs.end(), scat.begin(), scat.end());
     b->offs.insert(b->offs.end(), sort.begin(), sort.end());
     b->offs.insert(b->offs.end(), qoff.begin(), qoff.end());
+    b->offs.insert(b->offs.end(), grab.begin(), grab.end());
     return AUV_OK;
 }
 
@@ -437,7 +460,7 @@ Tables table_ptrs(const auv_batch *b, char *ws)
     t.idw = reinterpret_cast<IdwItem *>(ws + off);
     off += align256(sizeof(IdwItem) * count);
     t.offs = reinterpret_cast<int32_t *>(ws + off);
-    off += align256(sizeof(int32_t) * (3 * (count + 1) + 2 * kQueues + 1));
+    off += align256(sizeof(int32_t) * (3 * (count + 1) + 4 * kQueues + 1));
     t.qhead = reinterpret_cast<int32_t *>(ws + off);
     off += align256(sizeof(int32_t) * 2 * kQueues);
     t.work = reinterpret_cast<int2 *>(ws + off);
@@ -447,7 +470,7 @@ Tables table_ptrs(const auv_batch *b, char *ws)
 size_t tables_size(size_t count, size_t max_tiles)
 {
     return align256(sizeof(RowItem) * count) + align256(sizeof(IdwItem) * count) +
-           align256(sizeof(int32_t) * (3 * (count + 1) + 2 * kQueues + 1)) +
+           align256(sizeof(int32_t) * (3 * (count + 1) + 4 * kQueues + 1)) +
            align256(sizeof(int32_t) * 2 * kQueues) +
            align256(sizeof(int2) * std::max<size_t>(max_tiles, 1));
 }
@@ -473,22 +496,20 @@ auv_status enqueue_batched(auv_batch *b, char *ws, hipStream_t st)
     }
     if (!b->work.empty()) {
         k_reset_queues<<<1, 64, 0, st>>>(t.qhead);
-        int dev = 0, cus = 256;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         const int32_t *qoff = t.offs + 3 * (nr + 1);
+        const int32_t *qgrab = qoff + 2 * kQueues + 1;
         // the dense form runs on a forked branch of the graph, concurrently
         if (b->nwork_dense > 0) {
             AUV_HIP(hipEventRecord(b->ev_fork, st));
             AUV_HIP(hipStreamWaitEvent(b->cap_stream2, b->ev_fork, 0));
-            k_idw_batch_dense<<<std::min<int>(b->nwork_dense, cus * 8), 64, 0, b->cap_stream2>>>(
-                t.idw, t.work, qoff + kQueues, t.qhead + kQueues);
+            k_idw_batch_dense<<<b->blocks_dense, 64, 0, b->cap_stream2>>>(
+                t.idw, t.work, qoff + kQueues, qgrab + kQueues, t.qhead + kQueues);
             AUV_HIP(hipGetLastError());
             AUV_HIP(hipEventRecord(b->ev_join, b->cap_stream2));
         }
         if (b->nwork_window > 0)
-            k_idw_batch_window<<<std::min<int>(b->nwork_window, cus * 16), 64, 0, st>>>(
-                t.idw, t.work, qoff, t.qhead);
+            k_idw_batch_window<<<b->blocks_window, 64, 0, st>>>(t.idw, t.work, qoff, qgrab,
+                                                               t.qhead);
         AUV_HIP(hipGetLastError());
         if (b->nwork_dense > 0)
             AUV_HIP(hipStreamWaitEvent(st, b->ev_join, 0));
