@@ -89,7 +89,8 @@ typedef struct {
 /* Kernel forms of auv_interp_idw. */
 enum {
     AUV_ALGO_AUTO = 0,   /* dense form when the expected disk population is at
-                            least max_pts (and 1 <= max_pts <= 32), else sparse */
+                            least max_pts / 2 (and 1 <= max_pts <= 32): many
+                            nodes would exceed the cap; else sparse */
     AUV_ALGO_SPARSE = 1, /* node windows scattered from each sounding */
     AUV_ALGO_DENSE = 2   /* per-node ring search with a register top-k list;
                             needs 1 <= max_pts <= 32 and AUV_P_FP32_REBASE */

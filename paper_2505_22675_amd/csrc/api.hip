@@ -297,7 +297,7 @@ auv_status auv_interp_idw(const auv_grid *grid, const auv_bins *bins,
             return fail(AUV_ERR_INVALID,
                         "the dense form needs 1 <= max_pts <= 32 and AUV_P_FP32_REBASE");
         a.dense = params->algo == AUV_ALGO_DENSE ||
-                  (params->algo == AUV_ALGO_AUTO && dense_ok && lambda >= params->max_pts);
+                  (params->algo == AUV_ALGO_AUTO && dense_ok && lambda >= 0.5 * params->max_pts);
     }
     a.z_out = z_out;
     a.cnt_out = cnt_out;

@@ -196,8 +196,10 @@ std::vector<Choice> candidates(const auv_batch_item &it, int32_t sR)
     for (int d = -1; d <= 1 && sparse_ok; ++d)
         if (sR + d >= 12 && sR + d <= 26)
             c.push_back({sR + d, AUV_ALGO_SPARSE});
+    // dense: bins down to 1/64 of the default side (very dense tiles want bins
+    // holding a few soundings, so the ring search stops after a few rings)
     if (dense_allowed(it) && disk_population(it) >= 0.5 * it.params.max_pts)
-        for (int d = -4; d <= -1; ++d)
+        for (int d = -6; d <= -1; ++d)
             if (sR + d >= 12)
                 c.push_back({sR + d, AUV_ALGO_DENSE});
     return c;
@@ -315,7 +317,7 @@ int32_t auto_algo(const auv_batch_item &it)
 {
     if (it.params.algo != AUV_ALGO_AUTO)
         return it.params.algo;
-    return dense_allowed(it) && disk_population(it) >= it.params.max_pts ? AUV_ALGO_DENSE
+    return dense_allowed(it) && disk_population(it) >= 0.5 * it.params.max_pts ? AUV_ALGO_DENSE
                                                                           : AUV_ALGO_SPARSE;
 }
 

@@ -59,15 +59,14 @@ __device__ inline float wfast(float d2, int pmode, float power, float inv_r2)
     return __builtin_amdgcn_exp2f(-0.5f * power * __builtin_amdgcn_logf(d2 * inv_r2));
 }
 
+// Exact value of node (row an, column b) by one lane (no wave-wide operations,
+// so any subset of lanes may call it): ring search for the max_pts nearest
+// keys (max_pts <= KMAX), then the weighted sum in key order.  Writes the
+// node's outputs.
 template <int kMode, int KMAX>
-__device__ void dense_tile(const auv_bin_view &bv, const IdwArgs &a, int tile, int ntx,
-                           int pmode)
+__device__ void dense_node(const auv_bin_view &bv, const IdwArgs &a, int b, int an, int pmode)
 {
     constexpr bool kIdw = (kMode & 1) != 0;
-    const int lane = threadIdx.x & 63;
-    const int tx = tile % ntx, ty = tile / ntx;
-    const int b = tx * kDT + (lane % kDT), an = ty * kDT + (lane / kDT);
-    const bool active = b < a.nx && an < a.ny;
     const NodeL nx_l = node_lat(b, a.dx), ny_l = node_lat(an, a.dy);
     const int Xn = nx_l.X, Yn = ny_l.X;
     const int s = bv.bin_log2;
@@ -116,7 +115,7 @@ __device__ void dense_tile(const auv_bin_view &bv, const IdwArgs &a, int tile, i
             consider(k);
     };
 
-    if (active) {
+    {
         for (int d = 0;; ++d) {
             segment(byn - d, bxn - d, bxn + d);
             if (d > 0) {
@@ -135,8 +134,6 @@ __device__ void dense_tile(const auv_bin_view &bv, const IdwArgs &a, int tile, i
         }
     }
 
-    if (!active)
-        return;
     const int m = min(found, kcap);
     const int64_t o = (int64_t)an * a.nx + b;
     const unsigned long long imask = (1ull << kb) - 1ull;
@@ -192,6 +189,18 @@ __device__ void dense_tile(const auv_bin_view &bv, const IdwArgs &a, int tile, i
         }
         a.z_out[o] = v;
     }
+}
+
+// One 64-lane wave per 8 x 8 node tile, one node per lane.
+template <int kMode, int KMAX>
+__device__ void dense_tile(const auv_bin_view &bv, const IdwArgs &a, int tile, int ntx,
+                           int pmode)
+{
+    const int lane = threadIdx.x & 63;
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int b = tx * kDT + (lane % kDT), an = ty * kDT + (lane / kDT);
+    if (b < a.nx && an < a.ny)
+        dense_node<kMode, KMAX>(bv, a, b, an, pmode);
 }
 
 template <int kMode, int KMAX>

@@ -236,58 +236,13 @@ __device__ void exact_node(const auv_bin_view &bv, const IdwArgs &a, int X0, int
         return kv <= R2 ? kv : -1.0;
     };
     const int kcap = a.max_pts;
-    // smallest T in [0, R2] with #{D^2 <= T} >= k
-    double lo = 0.0, hi = R2;
-    while (lo < hi) {
-        const double mid = floor((lo + hi) * 0.5);
-        int c = 0;
-        for_each_candidate(bv, sg, [&](int k) {
-            const double kv = k >= 0 ? member_key(k) : -1.0;
-            c += wave_count(kv >= 0.0 && kv <= mid);
-        });
-        if (c >= kcap)
-            hi = mid;
-        else
-            lo = mid + 1.0;
-    }
-    const double T = lo;
-    int clt = 0, ceq = 0;
-    for_each_candidate(bv, sg, [&](int k) {
-        const double d2 = k >= 0 ? member_key(k) : -1.0;
-        clt += wave_count(d2 >= 0.0 && d2 < T);
-        ceq += wave_count(d2 >= 0.0 && d2 == T);
-    });
-    const int need = kcap - clt;
-    long long J = INT_MAX;
-    if (ceq > need) {
-        long long jlo = 0, jhi = INT_MAX;
-        while (jlo < jhi) {
-            const long long mid = (jlo + jhi) >> 1;
-            int c = 0;
-            for_each_candidate(bv, sg, [&](int k) {
-                c += wave_count(k >= 0 && member_key(k) == T && bv.idx[k] <= mid);
-            });
-            if (c >= need)
-                jhi = mid;
-            else
-                jlo = mid + 1;
-        }
-        J = jlo;
-    }
-    // accumulate the selected set (per lane, then reduced over the wave)
+    // accumulate one selected member (per lane, reduced over the wave below)
     float num = 0.0f, den = 0.0f, emax = -INFINITY;
     int cnt = 0, hits = 0;
     double hsum = 0.0, bd2 = 1e300;
     int bidx = INT_MAX;
     float bz = 0.0f;
-    for_each_candidate(bv, sg, [&](int k) {
-        if (k < 0)
-            return;
-        float d2f;
-        const double d2 = cand_key<kPrec>(bv, a, k, Xn, Yn, na, nb, X0, Y0, DXl, DYl, &d2f);
-        const int ci = bv.idx[k];
-        if (!(d2 <= R2) || !(d2 < T || (d2 == T && ci <= J)))
-            return;
+    auto take = [&](int k, double d2, float d2f, int ci) {
         const float z = bv.z[k];
         cnt += 1;
         if (d2 < bd2 || (d2 == bd2 && ci < bidx)) {
@@ -317,7 +272,128 @@ __device__ void exact_node(const auv_bin_view &bv, const IdwArgs &a, int X0, int
                 den += w;
             }
         }
-    });
+    };
+    // Fast path (exact lattice keys): gather the node's members once into
+    // registers, up to kHold per lane, as unique packed keys (D^2 << b | index);
+    // find the cap-th smallest key by bisection over the held keys (no memory
+    // traffic), then take the members at or below it.
+    constexpr int kHold = 4;
+    bool done = false;
+    if constexpr (kPrec == AUV_P_FP32_REBASE) {
+        const int kb = bv.idx_bits;
+        const long long R2i = (long long)a.R * a.R;
+        if ((unsigned long long)R2i < (1ull << (63 - kb))) {
+            unsigned long long mk[kHold];
+            int mpos[kHold];
+#pragma unroll
+            for (int j = 0; j < kHold; ++j) {
+                mk[j] = ~0ull;
+                mpos[j] = -1;
+            }
+            int held = 0;
+            bool over = false;
+            for_each_candidate(bv, sg, [&](int k) {
+                if (k < 0)
+                    return;
+                const long long dX = bv.X[k] - Xn, dY = bv.Y[k] - Yn;
+                const long long D2 = dX * dX + dY * dY;
+                if (D2 > R2i)
+                    return;
+                const unsigned long long key = ((unsigned long long)D2 << kb) | (unsigned)bv.idx[k];
+#pragma unroll
+                for (int j = 0; j < kHold; ++j)
+                    if (held == j) {
+                        mk[j] = key;
+                        mpos[j] = k;
+                    }
+                over |= held >= kHold;
+                held += 1;
+            });
+            if (!__ballot(over)) {
+                unsigned long long lo = 0ull, hi = 0ull;
+#pragma unroll
+                for (int j = 0; j < kHold; ++j)
+                    hi = mpos[j] >= 0 && mk[j] > hi ? mk[j] : hi;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const unsigned long long o = __shfl_xor(hi, d, 64);
+                    hi = o > hi ? o : hi;
+                }
+                // smallest key with at least kcap members at or below it
+                while (lo < hi) {
+                    const unsigned long long mid = lo + ((hi - lo) >> 1);
+                    int c = 0;
+#pragma unroll
+                    for (int j = 0; j < kHold; ++j)
+                        c += mpos[j] >= 0 && mk[j] <= mid ? 1 : 0;
+                    if (wave_sum_i(c) >= kcap)
+                        hi = mid;
+                    else
+                        lo = mid + 1ull;
+                }
+#pragma unroll
+                for (int j = 0; j < kHold; ++j) {
+                    if (mpos[j] >= 0 && mk[j] <= lo) {
+                        float d2f;
+                        const double d2 = cand_key<kPrec>(bv, a, mpos[j], Xn, Yn, na, nb, X0, Y0,
+                                                          DXl, DYl, &d2f);
+                        take(mpos[j], d2, d2f, (int)(mk[j] & ((1ull << kb) - 1ull)));
+                    }
+                }
+                done = true;
+            }
+        }
+    }
+    if (!done) {
+        // general path: smallest T in [0, R2] with #{D^2 <= T} >= k
+        double lo = 0.0, hi = R2;
+        while (lo < hi) {
+            const double mid = floor((lo + hi) * 0.5);
+            int c = 0;
+            for_each_candidate(bv, sg, [&](int k) {
+                const double kv = k >= 0 ? member_key(k) : -1.0;
+                c += wave_count(kv >= 0.0 && kv <= mid);
+            });
+            if (c >= kcap)
+                hi = mid;
+            else
+                lo = mid + 1.0;
+        }
+        const double T = lo;
+        int clt = 0, ceq = 0;
+        for_each_candidate(bv, sg, [&](int k) {
+            const double d2 = k >= 0 ? member_key(k) : -1.0;
+            clt += wave_count(d2 >= 0.0 && d2 < T);
+            ceq += wave_count(d2 >= 0.0 && d2 == T);
+        });
+        const int need = kcap - clt;
+        long long J = INT_MAX;
+        if (ceq > need) {
+            long long jlo = 0, jhi = INT_MAX;
+            while (jlo < jhi) {
+                const long long mid = (jlo + jhi) >> 1;
+                int c = 0;
+                for_each_candidate(bv, sg, [&](int k) {
+                    c += wave_count(k >= 0 && member_key(k) == T && bv.idx[k] <= mid);
+                });
+                if (c >= need)
+                    jhi = mid;
+                else
+                    jlo = mid + 1;
+            }
+            J = jlo;
+        }
+        for_each_candidate(bv, sg, [&](int k) {
+            if (k < 0)
+                return;
+            float d2f;
+            const double d2 = cand_key<kPrec>(bv, a, k, Xn, Yn, na, nb, X0, Y0, DXl, DYl, &d2f);
+            const int ci = bv.idx[k];
+            if (!(d2 <= R2) || !(d2 < T || (d2 == T && ci <= J)))
+                return;
+            take(k, d2, d2f, ci);
+        });
+    }
     cnt = wave_sum_i(cnt);
     wave_best(bd2, bidx, bz);
     const int64_t o = (int64_t)na * a.nx + nb;
