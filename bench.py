@@ -38,7 +38,7 @@ def host_threads() -> int:
 # Sources that define each profiled kernel (its code and its argument structs).
 KERNEL_SOURCES = {
     "k_idw_window": ["idw_window_impl.hpp", "idw_window.hip", "auv_internal.hpp"],
-    "k_bilinear": ["bilinear_kernels.hip", "auv_internal.hpp"],
+    "k_bilinear": ["bilinear_kernels.hip", "resample_axis.hpp", "auv_internal.hpp"],
 }
 
 
@@ -416,6 +416,28 @@ def main():
                "nan_nodes": int(torch.isnan(cub).sum().item())}
     log(f"bicubic 2x: {cub_ms:.4f} ms ({cub_gbs:.0f} GB/s)")
 
+    # next row: ordinary kriging 2x of the same grid, range three source cells
+    krig = torch.empty_like(up)
+    krig_range = 3.0 * s.grid.dx
+    for _ in range(3):
+        ag.auv_resample_kriging(z_out, s.grid, krig, up_desc, krig_range, stream=stream)
+    ke = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(20)]
+    for e0, e1 in ke:
+        e0.record(stream)
+        ag.auv_resample_kriging(z_out, s.grid, krig, up_desc, krig_range, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    krig_ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ke]))
+    krig_gbs = alg["bilinear"] / (krig_ms * 1e-3) / 1e9
+    kriging = {"workload": "ordinary kriging 2x of the 4096^2 IDW grid to 8192^2, 5x5 window, "
+                           f"exponential variogram range {krig_range:g} m, bilinear fallback at "
+                           "NaN windows", "ms": round(krig_ms, 5),
+               "nodes_per_s": round(up.numel() / (krig_ms * 1e-3), 1),
+               "achieved_GBs": round(krig_gbs, 1), "hbm_frac": round(krig_gbs / HBM_PEAK_GBS, 4),
+               "nan_nodes": int(torch.isnan(krig).sum().item())}
+    log(f"kriging 2x: {krig_ms:.4f} ms ({krig_gbs:.0f} GB/s)")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(s, up_desc, nodes)
@@ -449,6 +471,7 @@ def main():
         "cpu_baseline": cpu,
         "precision_utm": precision,
         "bicubic": bicubic,
+        "kriging": kriging,
         "batched_tiles": batched,
         "serving": serving,
     }

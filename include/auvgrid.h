@@ -205,6 +205,21 @@ auv_status auv_resample_bicubic(const float *src, const auv_grid_desc *s,
                                 float *dst, const auv_grid_desc *d,
                                 auv_stream stream);
 
+/* Ordinary-kriging resample (Sec. III-C) with the node mapping of
+ * auv_resample_bilinear.  Neighbourhood: the 5 x 5 source nodes centred on
+ * the source node nearest to the destination point, moved inward at the grid
+ * edges.  Variogram: exponential, gamma(h) = C0 (1 - exp(-h / range)) with h
+ * in metres (the sill C0 cancels from the weights, so only `range` is
+ * given).  The weights solve the 26 x 26 ordinary-kriging system (unbiasedness
+ * row included); z = sum of weights x depths.  A neighbourhood with a
+ * non-finite value, or a source grid under 5 x 5, falls back to the bilinear
+ * value (a hole when one of its corners is NaN).  FP32 arithmetic on depths
+ * relative to the window centre.  Errors as auv_resample_bilinear, plus
+ * AUV_ERR_INVALID for a non-positive range. */
+auv_status auv_resample_kriging(const float *src, const auv_grid_desc *s,
+                                float *dst, const auv_grid_desc *d, double range,
+                                auv_stream stream);
+
 /* ------------------------------------------------------------ batches --
  * Many independent, uneven gridding problems ("items") run as one unit: one
  * set of batched binning launches and one persistent IDW launch per kernel

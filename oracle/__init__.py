@@ -79,8 +79,9 @@ def _load():
                                     vp, vp, i32]
         lib.orc_bilinear.argtypes = [P(_Grid), vp, P(_Grid), vp, i32]
         lib.orc_bicubic.argtypes = [P(_Grid), vp, P(_Grid), vp, i32]
+        lib.orc_kriging.argtypes = [P(_Grid), vp, P(_Grid), d, vp, i32]
         for f in (lib.orc_bin_dims, lib.orc_bin, lib.orc_idw, lib.orc_nearest,
-                  lib.orc_bilinear, lib.orc_bicubic):
+                  lib.orc_bilinear, lib.orc_bicubic, lib.orc_kriging):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -200,4 +201,16 @@ def bicubic(src_grid: Grid, src, dst_grid: Grid, nthreads: int = 0):
     _check(lib.orc_bicubic(ctypes.byref(src_grid.c()), _ptr(s),
                            ctypes.byref(dst_grid.c()), _ptr(d), nthreads),
            "orc_bicubic")
+    return d.reshape(dst_grid.ny, dst_grid.nx)
+
+
+def kriging(src_grid: Grid, src, dst_grid: Grid, range_m: float, nthreads: int = 0):
+    """O6: ordinary kriging (5 x 5 neighbourhood, exponential variogram)."""
+    lib = _load()
+    s = _f64(src).reshape(-1)
+    if s.shape[0] != src_grid.nx * src_grid.ny:
+        raise ValueError("source size does not match its grid")
+    d = np.empty(dst_grid.nx * dst_grid.ny, dtype=np.float64)
+    _check(lib.orc_kriging(ctypes.byref(src_grid.c()), _ptr(s), ctypes.byref(dst_grid.c()),
+                           float(range_m), _ptr(d), nthreads), "orc_kriging")
     return d.reshape(dst_grid.ny, dst_grid.nx)

@@ -595,3 +595,122 @@ int orc_bicubic(const orc_grid *sg, const double *src, const orc_grid *dg,
     }
     return ORC_OK;
 }
+
+/* ---------------------------------------------------------------- kriging -- */
+
+/* Exponential variogram (Sec. III-C) with unit sill: the sill scales the
+ * whole system and cancels from the weights. */
+static double orc_gamma(double h, double a) { return 1.0 - exp(-h / a); }
+
+/* Solve A x = b (n x n, row-major, overwritten) by Gaussian elimination with
+ * partial pivoting.  Returns 0 when a pivot vanishes. */
+static int orc_gauss_solve(double *A, double *b, int n)
+{
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(A[r * n + c]) > fabs(A[p * n + c]))
+                p = r;
+        if (A[p * n + c] == 0.0)
+            return 0;
+        if (p != c) {
+            for (int k = 0; k < n; ++k) {
+                double t = A[c * n + k];
+                A[c * n + k] = A[p * n + k];
+                A[p * n + k] = t;
+            }
+            double t = b[c];
+            b[c] = b[p];
+            b[p] = t;
+        }
+        for (int r = c + 1; r < n; ++r) {
+            double f = A[r * n + c] / A[c * n + c];
+            for (int k = c; k < n; ++k)
+                A[r * n + k] -= f * A[c * n + k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double v = b[r];
+        for (int k = r + 1; k < n; ++k)
+            v -= A[r * n + k] * b[k];
+        b[r] = v / A[r * n + r];
+    }
+    return 1;
+}
+
+/* First index of the 5-node window centred on the node nearest to index
+ * coordinate u (already clamped to [0, n-1]), moved inward at the edges. */
+static int32_t orc_window_start(double u, int32_t n)
+{
+    int32_t c = (int32_t)floor(u + 0.5);
+    int32_t s = c - 2;
+    if (s > n - 5)
+        s = n - 5;
+    if (s < 0)
+        s = 0;
+    return s;
+}
+
+int orc_kriging(const orc_grid *sg, const double *src, const orc_grid *dg, double range,
+                double *dst, int32_t nthreads)
+{
+    if (!orc_grid_ok(sg) || !orc_grid_ok(dg) || !(range > 0.0) || !isfinite(range))
+        return ORC_EINVAL;
+    if (nthreads <= 0)
+        nthreads = omp_get_max_threads();
+    const int small = sg->nx < 5 || sg->ny < 5;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int64_t a = 0; a < dg->ny; ++a) {
+        int32_t j0, j1;
+        double s;
+        orc_axis(dg->y0, dg->dy, (int32_t)a, sg->y0, sg->dy, sg->ny, &j0, &j1, &s);
+        for (int32_t b = 0; b < dg->nx; ++b) {
+            int32_t i0, i1;
+            double t;
+            orc_axis(dg->x0, dg->dx, b, sg->x0, sg->dx, sg->nx, &i0, &i1, &t);
+            double v;
+            int ok = !small;
+            int32_t wx = 0, wy = 0;
+            if (ok) {
+                /* the destination point in source index units (as bilinear) */
+                double u = i0 + t, w = j0 + s;
+                wx = orc_window_start(u, sg->nx);
+                wy = orc_window_start(w, sg->ny);
+                for (int k = 0; k < 25 && ok; ++k)
+                    ok = isfinite(src[(int64_t)(wy + k / 5) * sg->nx + wx + k % 5]);
+            }
+            if (ok) {
+                /* ordinary kriging system: variogram between the 25 window
+                 * nodes, the unbiasedness row and column, and the variogram
+                 * between each node and the destination point */
+                double A[26 * 26], rhs[26];
+                double u = i0 + t, w = j0 + s;
+                for (int p = 0; p < 25; ++p) {
+                    double xp = (wx + p % 5) * sg->dx, yp = (wy + p / 5) * sg->dy;
+                    for (int q = 0; q < 25; ++q) {
+                        double xq = (wx + q % 5) * sg->dx, yq = (wy + q / 5) * sg->dy;
+                        A[p * 26 + q] = orc_gamma(hypot(xp - xq, yp - yq), range);
+                    }
+                    A[p * 26 + 25] = 1.0;
+                    A[25 * 26 + p] = 1.0;
+                    rhs[p] = orc_gamma(hypot(xp - u * sg->dx, yp - w * sg->dy), range);
+                }
+                A[25 * 26 + 25] = 0.0;
+                rhs[25] = 1.0;
+                if (orc_gauss_solve(A, rhs, 26)) {
+                    v = 0.0;
+                    for (int p = 0; p < 25; ++p)
+                        v += rhs[p] * src[(int64_t)(wy + p / 5) * sg->nx + wx + p % 5];
+                } else {
+                    v = orc_bilinear_at(sg, src, i0, i1, t, j0, j1, s);
+                }
+            } else {
+                /* an invalid neighbour (or a grid under 5 x 5): bilinear */
+                v = orc_bilinear_at(sg, src, i0, i1, t, j0, j1, s);
+            }
+            dst[a * dg->nx + b] = v;
+        }
+    }
+    return ORC_OK;
+}

@@ -89,6 +89,17 @@ int orc_bilinear(const orc_grid *src_g, const double *src, const orc_grid *dst_g
 int orc_bicubic(const orc_grid *src_g, const double *src, const orc_grid *dst_g,
                 double *dst, int32_t nthreads);
 
+/* O6: ordinary kriging resample (Sec. III-C): the 5 x 5 source nodes centred
+ * on the node nearest to the destination point (same index coordinate as O3;
+ * the window moves inward at the grid edges), the exponential variogram
+ * gamma(h) = 1 - exp(-h / range) (h in metres; the sill cancels from the
+ * weights), the 26 x 26 system with the unbiasedness row solved by Gaussian
+ * elimination with partial pivoting, and z = sum of weights x depths.  Any
+ * non-finite window value (or a grid under 5 x 5) falls back to O3's
+ * bilinear value, as the cubic does. */
+int orc_kriging(const orc_grid *src_g, const double *src, const orc_grid *dst_g,
+                double range, double *dst, int32_t nthreads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -112,6 +112,8 @@ def load_library(path: str = LIB_PATH):
                                   ctypes.c_int),
         "auv_resample_bicubic": ([vp, P(auv_grid_desc), vp, P(auv_grid_desc), vp],
                                  ctypes.c_int),
+        "auv_resample_kriging": ([vp, P(auv_grid_desc), vp, P(auv_grid_desc), d, vp],
+                                 ctypes.c_int),
         "auv_batch_plan": ([P(auv_batch_item), i32, ctypes.c_char_p, P(vp)], ctypes.c_int),
         "auv_batch_workspace_size": ([vp, P(ctypes.c_size_t)], ctypes.c_int),
         "auv_batch_launch": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
@@ -334,6 +336,19 @@ def auv_resample_bicubic(src: torch.Tensor, s_desc, dst: torch.Tensor, d_desc, s
         _dev(src, torch.float32, "src", s_desc.nx * s_desc.ny), ctypes.byref(s_desc),
         _dev(dst, torch.float32, "dst", d_desc.nx * d_desc.ny), ctypes.byref(d_desc),
         _stream(stream)))
+
+
+def auv_resample_kriging(src: torch.Tensor, s_desc, dst: torch.Tensor, d_desc, range_m: float,
+                         stream=None):
+    lib = load_library()
+    if not isinstance(s_desc, auv_grid_desc):
+        s_desc = make_desc(s_desc.x0, s_desc.y0, s_desc.dx, s_desc.dy, s_desc.nx, s_desc.ny)
+    if not isinstance(d_desc, auv_grid_desc):
+        d_desc = make_desc(d_desc.x0, d_desc.y0, d_desc.dx, d_desc.dy, d_desc.nx, d_desc.ny)
+    _check(lib.auv_resample_kriging(
+        _dev(src, torch.float32, "src", s_desc.nx * s_desc.ny), ctypes.byref(s_desc),
+        _dev(dst, torch.float32, "dst", d_desc.nx * d_desc.ny), ctypes.byref(d_desc),
+        float(range_m), _stream(stream)))
 
 
 # ------------------------------------------------------------ conveniences --

@@ -342,4 +342,14 @@ auv_status auv_resample_bicubic(const float *src, const auv_grid_desc *s, float 
     return launch_bicubic(src, *s, dst, *d, static_cast<hipStream_t>(stream));
 }
 
+auv_status auv_resample_kriging(const float *src, const auv_grid_desc *s, float *dst,
+                                const auv_grid_desc *d, double range, auv_stream stream)
+{
+    AUV_TRY(check_desc(s));
+    AUV_TRY(check_desc(d));
+    AUV_TRY(check_device_ptr(src, "src"));
+    AUV_TRY(check_device_ptr(dst, "dst"));
+    return launch_kriging(src, *s, dst, *d, range, static_cast<hipStream_t>(stream));
+}
+
 }  // extern "C"

@@ -209,5 +209,7 @@ auv_status launch_bilinear(const float *src, const auv_grid_desc &s, float *dst,
                            const auv_grid_desc &d, hipStream_t st);
 auv_status launch_bicubic(const float *src, const auv_grid_desc &s, float *dst,
                           const auv_grid_desc &d, hipStream_t st);
+auv_status launch_kriging(const float *src, const auv_grid_desc &s, float *dst,
+                          const auv_grid_desc &d, double range, hipStream_t st);
 
 }  // namespace auv

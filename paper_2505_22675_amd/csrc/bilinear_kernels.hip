@@ -5,7 +5,7 @@
 // operations, in the same order, as its definition (no contraction), so the
 // corner choice is exact; the blend itself is FP32 in lerp form (top, bottom, then vertical),
 // which keeps constants exact and lets a NaN corner propagate: a hole.
-#include "auv_internal.hpp"
+#include "resample_axis.hpp"
 
 #include <algorithm>
 #include <climits>
@@ -15,26 +15,6 @@ namespace auv {
 
 namespace {
 
-struct Axis {
-    int i0, i1;
-    float t;
-};
-
-__device__ inline Axis axis_of(double x0d, double dd, int j, double x0s, double ds,
-                               int ns)
-{
-#pragma clang fp contract(off)
-    const double xd = x0d + ((double)j + 0.5) * dd;
-    double u = (xd - x0s) / ds - 0.5;
-    u = u < 0.0 ? 0.0 : u;
-    u = u > (double)(ns - 1) ? (double)(ns - 1) : u;
-    const double f = floor(u);
-    Axis a;
-    a.i0 = (int)f;
-    a.i1 = a.i0 + 1 < ns ? a.i0 + 1 : ns - 1;
-    a.t = (float)(u - f);
-    return a;
-}
 
 struct BilArgs {
     const float *src;

@@ -1,0 +1,272 @@
+// Ordinary kriging resample of one grid onto another (Sec. III-C).
+//
+// A destination node maps to the source index coordinate u (as in the
+// bilinear resample); its neighbourhood is the 5 x 5 source nodes centred on
+// the node nearest to u, moved inward at the grid edges.  The weights solve
+// the ordinary-kriging system
+//     [ G  1 ] [ lambda ]   [ g ]
+//     [ 1' 0 ] [   mu   ] = [ 1 ]
+// with G the variogram between the 25 nodes, g the variogram between each node
+// and the destination point and gamma(h) = 1 - exp(-h / a) (the sill cancels
+// from the weights).  G depends only on the node spacing and the range, not
+// on where the window sits, so the 26 x 26 matrix is inverted once on the
+// host (FP64, Gauss-Jordan with partial pivoting) and each node costs a
+// matrix-vector product.  Written as
+//     z = z_c + sum_j g_j w_j,   w = K^-T (z - z_c, 0)
+// (z_c: the window centre), w depends only on the window, so a thread walking
+// down a column computes it once per window and each node adds one 26-term
+// product.  A window with a non-finite value falls back to bilinear.
+#include "resample_axis.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+
+namespace auv {
+
+namespace {
+
+constexpr int kKrigCols = 256;    // destination columns per block (one per thread)
+constexpr int kKrigRows = 8;      // destination rows per block
+constexpr int kKrigStage = 6144;  // source values staged in LDS
+
+struct KrigArgs {
+    const float *src;
+    float *dst;
+    double sx0, sy0, sdx, sdy;
+    double dx0, dy0, ddx, ddy;
+    int snx, sny, dnx, dny;
+    float fdx, fdy;  // source spacing
+    float c2;        // (log2(e) / range)^2
+    // rows 0..24 and 25 of the inverse kriging matrix restricted to its first
+    // 25 columns, transposed: kt[j * 25 + q] = Kinv[q][j]
+    float kt[26 * 25];
+};
+
+using cfloat = const __attribute__((address_space(4))) float;
+
+// First index of the 5-node window centred on the node nearest to u.
+__device__ inline int window_start(double u, int n)
+{
+    const int c = (int)floor(u + 0.5);
+    return min(max(c - 2, 0), n - 5);
+}
+
+// The inverse of the kriging matrix K = [G 1; 1' 0] splits as [A b; b' c]
+// with 1'A = 0 and 1'b = 1 (the weights A g + b sum to one for any g).  For
+// w = K^-1 (z - z_c, 0), sum_q w_q = 0, so with g_q = 1 - e_q,
+// e_q = exp(-h_q / range):
+//     z = z_c + sum_q g_q w_q + w_25 = z_c + w_25 - sum_q e_q w_q.
+__global__ __launch_bounds__(kKrigCols) void k_kriging(const KrigArgs p)
+{
+    __shared__ int s_wx[kKrigCols], s_i0[kKrigCols], s_i1[kKrigCols];
+    __shared__ float s_du[kKrigCols], s_t[kKrigCols];
+    __shared__ int s_wy[kKrigRows], s_j0[kKrigRows], s_j1[kKrigRows];
+    __shared__ float s_dv[kKrigRows], s_s[kKrigRows];
+    __shared__ float s_src[kKrigStage];
+    const int col0 = blockIdx.x * kKrigCols;
+    const int row0 = blockIdx.y * kKrigRows;
+    const int ncol = min(kKrigCols, p.dnx - col0);
+    const int nrow = min(kKrigRows, p.dny - row0);
+    {
+        const int c = threadIdx.x;
+        const Axis a = axis_of(p.dx0, p.ddx, min(col0 + c, p.dnx - 1), p.sx0, p.sdx, p.snx);
+        const int wx = window_start(a.u, p.snx);
+        s_wx[c] = wx;
+        s_du[c] = (float)(a.u - wx);
+        s_i0[c] = a.i0;
+        s_i1[c] = a.i1;
+        s_t[c] = a.t;
+    }
+    if (threadIdx.x < kKrigRows) {
+        const int r = threadIdx.x;
+        const Axis a = axis_of(p.dy0, p.ddy, min(row0 + r, p.dny - 1), p.sy0, p.sdy, p.sny);
+        const int wy = window_start(a.u, p.sny);
+        s_wy[r] = wy;
+        s_dv[r] = (float)(a.u - wy);
+        s_j0[r] = a.i0;
+        s_j1[r] = a.i1;
+        s_s[r] = a.t;
+    }
+    __syncthreads();
+    // source rectangle of every window of the patch (window starts are
+    // monotone); the bilinear corners of a node lie inside its window
+    const int il = s_wx[0], ih = s_wx[ncol - 1] + 4;
+    const int jl = s_wy[0], jh = s_wy[nrow - 1] + 4;
+    const int sw = ih - il + 1, sh = jh - jl + 1;
+    const bool staged = (long long)sw * sh <= kKrigStage;
+    if (staged) {
+        for (int e = threadIdx.x; e < sw * sh; e += kKrigCols) {
+            const int r = e / sw, c = e - r * sw;
+            s_src[e] = p.src[(int64_t)(jl + r) * p.snx + il + c];
+        }
+        __syncthreads();
+    }
+    const int c = threadIdx.x;
+    if (c >= ncol)
+        return;
+    auto at = [&](int j, int i) {  // source value at row j, column i
+        return staged ? s_src[(j - jl) * sw + (i - il)] : p.src[(int64_t)j * p.snx + i];
+    };
+    const int wx = s_wx[c];
+    // squared x offsets to the window columns, scaled by (log2(e) / range)^2
+    float ex2[5];
+    {
+        const float du = s_du[c];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const float e = ((float)i - du) * p.fdx;
+            ex2[i] = e * e * p.c2;
+        }
+    }
+    float w[26];
+    float zc = 0.0f;
+    bool bad = false;
+    int cur = -1;  // window row start of w (the same for every thread of the block)
+    for (int r = 0; r < nrow; ++r) {
+        const int wy = s_wy[r];
+        if (wy != cur) {
+            float dz[25];
+            zc = at(wy + 2, wx + 2);
+            bad = false;
+#pragma unroll
+            for (int q = 0; q < 25; ++q) {
+                const float z = at(wy + q / 5, wx + q % 5);
+                bad |= !isfinite(z);
+                dz[q] = z - zc;
+            }
+            // the matrix is read from the argument segment through scalar
+            // loads here, once per window: an opaque pointer keeps the 650
+            // values from being held in registers across the row loop
+            cfloat *kt = (cfloat *)((const __attribute__((address_space(4))) char *)
+                                        __builtin_amdgcn_kernarg_segment_ptr() +
+                                    offsetof(KrigArgs, kt));
+            asm volatile("" : "+s"(kt));
+#pragma unroll
+            for (int j = 0; j < 26; ++j) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int q = 0; q < 25; ++q)
+                    acc = fmaf(kt[j * 25 + q], dz[q], acc);
+                w[j] = acc;
+            }
+            cur = wy;
+        }
+        float v;
+        if (bad) {
+            // a non-finite neighbour: bilinear on the node's cell corners
+            const int i0 = s_i0[c], i1 = s_i1[c], j0 = s_j0[r], j1 = s_j1[r];
+            const float t = s_t[c], s = s_s[r];
+            const float q00 = at(j0, i0), q10 = at(j0, i1);
+            const float q01 = at(j1, i0), q11 = at(j1, i1);
+            const float top = q00 + t * (q10 - q00);
+            const float bot = q01 + t * (q11 - q01);
+            v = top + s * (bot - top);
+        } else {
+            const float dv = s_dv[r];
+            float acc = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const float e = ((float)k - dv) * p.fdy;
+                const float ey2 = e * e * p.c2;
+#pragma unroll
+                for (int i = 0; i < 5; ++i) {
+                    const float h = __builtin_amdgcn_sqrtf(ex2[i] + ey2);
+                    acc = fmaf(__builtin_amdgcn_exp2f(-h), w[k * 5 + i], acc);
+                }
+            }
+            v = zc + (w[25] - acc);
+        }
+        p.dst[(int64_t)(row0 + r) * p.dnx + col0 + c] = v;
+    }
+}
+
+// Inverse of the 26 x 26 kriging matrix for node spacing (dx, dy) and range a,
+// by Gauss-Jordan elimination with partial pivoting in FP64.
+bool kriging_inverse(double dx, double dy, double range, double *out)
+{
+    constexpr int n = 26;
+    double A[n][2 * n];
+    for (int pi = 0; pi < 25; ++pi) {
+        for (int qi = 0; qi < 25; ++qi) {
+            const double h = std::hypot((pi % 5 - qi % 5) * dx, (pi / 5 - qi / 5) * dy);
+            A[pi][qi] = 1.0 - std::exp(-h / range);
+        }
+        A[pi][25] = 1.0;
+        A[25][pi] = 1.0;
+    }
+    A[25][25] = 0.0;
+    for (int r = 0; r < n; ++r)
+        for (int k = 0; k < n; ++k)
+            A[r][n + k] = r == k ? 1.0 : 0.0;
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (std::fabs(A[r][col]) > std::fabs(A[piv][col]))
+                piv = r;
+        if (!(std::fabs(A[piv][col]) > 0.0))
+            return false;
+        if (piv != col)
+            for (int k = 0; k < 2 * n; ++k)
+                std::swap(A[piv][k], A[col][k]);
+        const double d = A[col][col];
+        for (int k = 0; k < 2 * n; ++k)
+            A[col][k] /= d;
+        for (int r = 0; r < n; ++r) {
+            if (r == col || A[r][col] == 0.0)
+                continue;
+            const double f = A[r][col];
+            for (int k = 0; k < 2 * n; ++k)
+                A[r][k] -= f * A[col][k];
+        }
+    }
+    for (int r = 0; r < n; ++r)
+        for (int k = 0; k < n; ++k)
+            out[r * n + k] = A[r][n + k];
+    return true;
+}
+
+}  // namespace
+
+auv_status launch_kriging(const float *src, const auv_grid_desc &s, float *dst,
+                          const auv_grid_desc &d, double range, hipStream_t st)
+{
+    if (!(range > 0.0) || !std::isfinite(range))
+        return fail(AUV_ERR_INVALID, "range must be positive and finite");
+    if (s.nx < 5 || s.ny < 5)  // no 5 x 5 neighbourhood: every node is bilinear
+        return launch_bilinear(src, s, dst, d, st);
+    KrigArgs p;
+    std::memset(&p, 0, sizeof(p));
+    p.src = src;
+    p.dst = dst;
+    p.sx0 = s.x0;
+    p.sy0 = s.y0;
+    p.sdx = s.dx;
+    p.sdy = s.dy;
+    p.dx0 = d.x0;
+    p.dy0 = d.y0;
+    p.ddx = d.dx;
+    p.ddy = d.dy;
+    p.snx = s.nx;
+    p.sny = s.ny;
+    p.dnx = d.nx;
+    p.dny = d.ny;
+    p.fdx = (float)s.dx;
+    p.fdy = (float)s.dy;
+    const double l = 1.4426950408889634 / range;
+    p.c2 = (float)(l * l);
+    double kinv[26 * 26];
+    if (!kriging_inverse(s.dx, s.dy, range, kinv))
+        return fail(AUV_ERR_INVALID, "singular kriging system for this spacing and range");
+    for (int j = 0; j < 26; ++j)
+        for (int q = 0; q < 25; ++q)
+            p.kt[j * 25 + q] = (float)kinv[q * 26 + j];
+    const dim3 grid((unsigned)((d.nx + kKrigCols - 1) / kKrigCols),
+                    (unsigned)((d.ny + kKrigRows - 1) / kKrigRows));
+    k_kriging<<<grid, kKrigCols, 0, st>>>(p);
+    AUV_HIP(hipGetLastError());
+    return AUV_OK;
+}
+
+}  // namespace auv

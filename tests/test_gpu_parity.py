@@ -465,3 +465,92 @@ def test_idw_dense_form_parity(ag, orc, kcap, power, min_pts, snap, bin_log2):
     _assert_idw_equal(out2["z"].cpu().numpy(), out2["cnt"].cpu().numpy(),
                       out2["nn_idx"].cpu().numpy(), out2["nn_z"].cpu().numpy(), oz, oc, on, z,
                       f"sparse on dense k={kcap}")
+
+
+# ------------------------------------------------------------------ kriging --
+
+@pytest.mark.parametrize("src_shape,dst_shape,range_cells,nan_frac", [
+    ((37, 53), (74, 106), 3.0, 0.0),     # 2x upsample, several blocks and a ragged tail
+    ((64, 300), (21, 97), 0.5, 0.0),     # downsample: source patch not staged
+    ((40, 40), (160, 160), 10.0, 0.02),  # holes: windows with NaN fall back to bilinear
+    ((5, 5), (13, 11), 2.0, 0.0),        # the smallest grid with a 5 x 5 window
+    ((9, 600), (9, 1300), 1.0, 0.0),     # wide and flat: many column blocks
+])
+def test_kriging_parity(ag, orc, src_shape, dst_shape, range_cells, nan_frac):
+    sh, sw = src_shape
+    dh, dw = dst_shape
+    rng = np.random.default_rng(sh * 7919 + dw * 31 + int(range_cells * 10))
+    v = (-5000.0 + rng.normal(0, 400.0, (sh, sw))).astype(np.float32)
+    if nan_frac:
+        v[rng.random((sh, sw)) < nan_frac] = np.nan
+    from gen import GridSpec
+    sg = GridSpec(1000.0, 2000.0, 2.0, 3.0, sw, sh)
+    dg = GridSpec(1000.0, 2000.0, 2.0 * sw / dw, 3.0 * sh / dh, dw, dh)
+    rng_m = range_cells * 2.0
+    src = torch.from_numpy(v).cuda()
+    dst = torch.empty((dh, dw), dtype=torch.float32, device="cuda")
+    ag.auv_resample_kriging(src, sg, dst, dg, rng_m)
+    torch.cuda.synchronize()
+    ref = orc.kriging(_ogrid(orc, sg), v.astype(np.float64), _ogrid(orc, dg), rng_m)
+    out = dst.cpu().numpy().astype(np.float64)
+    assert np.array_equal(np.isnan(out), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    assert np.max(np.abs(out[ok] - ref[ok]) / np.abs(ref[ok])) <= REL
+
+
+def test_kriging_small_grid_is_bilinear(ag):
+    """A source grid under 5 x 5 has no kriging window: the entry point gives
+    exactly the bilinear resample."""
+    from gen import GridSpec
+    rng = np.random.default_rng(5)
+    v = (-100.0 + rng.normal(0, 5.0, (4, 9))).astype(np.float32)
+    sg = GridSpec(0.0, 0.0, 1.0, 1.0, 9, 4)
+    dg = GridSpec(0.0, 0.0, 0.5, 0.5, 18, 8)
+    src = torch.from_numpy(v).cuda()
+    a = torch.empty((8, 18), dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    ag.auv_resample_kriging(src, sg, a, dg, 3.0)
+    ag.auv_resample_bilinear(src, sg, b, dg)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_kriging_rejects_bad_range(ag):
+    from gen import GridSpec
+    g = GridSpec(0.0, 0.0, 1.0, 1.0, 8, 8)
+    src = torch.zeros((8, 8), dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for r in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(ag.AuvError):
+            ag.auv_resample_kriging(src, g, dst, g, r)
+
+
+def test_kriging_cfg2_upsample(ag, orc, cfg2_run):
+    """2x kriging resample of the full cfg2 IDW grid (holes included) to
+    8192^2 at 1 m, sampled rows against the oracle on a band of source rows
+    that holds the row's windows without moving them."""
+    s, res, grid, bins = cfg2_run
+    from gen import GridSpec
+    sg = s.grid
+    dg = GridSpec(0.0, 0.0, 1.0, 1.0, 8192, 8192)
+    rng_m = 3.0 * sg.dx
+    src = torch.from_numpy(res["z"]).cuda()
+    dst = torch.empty((8192, 8192), dtype=torch.float32, device="cuda")
+    ag.auv_resample_kriging(src, sg, dst, dg, rng_m)
+    torch.cuda.synchronize()
+    out = dst.cpu().numpy()
+    fallbacks = 0
+    for r in [0, 1, 2, 3, 4, 5, 4095, 4096, 8187, 8189, 8190, 8191, 1234, 7777, 5000]:
+        band_lo = max(0, r // 2 - 4)
+        band_hi = min(4096, r // 2 + 5)
+        sub = GridSpec(sg.x0, sg.y0 + band_lo * sg.dy, sg.dx, sg.dy, sg.nx, band_hi - band_lo)
+        drow = GridSpec(0.0, float(r), 1.0, 1.0, 8192, 1)
+        ref = orc.kriging(_ogrid(orc, sub), res["z"][band_lo:band_hi].astype(np.float64),
+                          _ogrid(orc, drow), rng_m)[0]
+        o = out[r].astype(np.float64)
+        assert np.array_equal(np.isnan(o), np.isnan(ref)), f"row {r}"
+        ok = ~np.isnan(ref)
+        fallbacks += int(np.isnan(res["z"][band_lo:band_hi]).any())
+        if ok.any():
+            assert np.max(np.abs(o[ok] - ref[ok]) / np.abs(ref[ok])) <= REL, f"row {r}"
+    assert fallbacks > 0
