@@ -104,6 +104,168 @@ def cpu_baseline(s, up_desc, nodes):
     return out
 
 
+def _median_ms(fn, stream, reps):
+    """Median HIP-event time of fn() on stream over reps launches (after two
+    untimed ones)."""
+    import numpy as np
+    import torch
+    fn()
+    fn()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
+
+
+GRID_A_POINTS = [10 ** 3, 10 ** 4, 10 ** 5, 10 ** 6, 10 ** 7, 10 ** 8]
+GRID_A_CPU_MAX = 10 ** 6
+RESAMPLERS = ("bilinear", "bicubic", "kriging")
+
+
+def cpu_grid_a(s, v, d, range_m):
+    """Oracle leg of the grid-A sweep: each resampler once, in ms."""
+    import oracle
+    oracle.build(force=False)
+    th = host_threads()
+    og = oracle.Grid(s.x0, s.y0, s.dx, s.dy, s.nx, s.ny)
+    od = oracle.Grid(d.x0, d.y0, d.dx, d.dy, d.nx, d.ny)
+    src = v.astype("float64")
+    out = {}
+    for m in RESAMPLERS:
+        c0 = time.perf_counter()
+        if m == "kriging":
+            oracle.kriging(og, src, od, range_m, nthreads=th)
+        else:
+            getattr(oracle, m)(og, src, od, nthreads=th)
+        out[f"cpu_{m}_ms"] = round((time.perf_counter() - c0) * 1e3, 3)
+    return out
+
+
+def grid_a_sweep(ag, dev, with_cpu):
+    """Row infill (grid A) from 1e3 to 1e8 interpolated nodes: median kernel
+    time of each resampler, and the oracle's time up to 1e6 nodes."""
+    import torch
+    from gen import grid_a_case
+    stream = torch.cuda.current_stream()
+    rows = []
+    for pts in GRID_A_POINTS:
+        s, v, d = grid_a_case(pts)
+        src = torch.from_numpy(v).to(dev)
+        dst = torch.empty((d.ny, d.nx), dtype=torch.float32, device=dev)
+        rm = 3.0 * s.dx
+        fns = {
+            "bilinear": lambda: ag.auv_resample_bilinear(src, s, dst, d, stream=stream),
+            "bicubic": lambda: ag.auv_resample_bicubic(src, s, dst, d, stream=stream),
+            "kriging": lambda: ag.auv_resample_kriging(src, s, dst, d, rm, stream=stream),
+        }
+        row = {"points": d.nx * d.ny, "src": [s.nx, s.ny]}
+        for m in RESAMPLERS:
+            row[f"gpu_{m}_ms"] = round(_median_ms(fns[m], stream, 20 if pts <= 10 ** 7 else 5), 5)
+        if with_cpu and pts <= GRID_A_CPU_MAX:
+            row.update(cpu_grid_a(s, v, d, rm))
+        rows.append(row)
+        log("grid A " + " ".join(f"{k}={v}" for k, v in row.items()))
+        del src, dst
+    return {"workload": "rows filled midway between the rows of a fractal-seafloor grid "
+                        "(1 m nodes), bilinear / Catmull-Rom / kriging (range 3 m)",
+            "rows": rows}
+
+
+def _fill_metrics(est, truth, interp):
+    import numpy as np
+    v = est[interp].astype(np.float64)
+    t = truth[interp]
+    ok = ~np.isnan(v)
+    e = v[ok] - t[ok]
+    return {"holes": int((~ok).sum()), "mae": round(float(np.abs(e).mean()), 5),
+            "rmse": round(float(np.sqrt((e * e).mean())), 5)}
+
+
+def grid_b_report(ag, dev, with_cpu, n_fine=2048):
+    """Random-removal infill (grid B) on a 2048^2 fractal-seafloor truth at
+    4 m: every other node recorded, 1 %, 5 % and 10 % of those removed, every
+    unrecorded node filled by the three resamplers (recorded grid -> fine grid)
+    and by the scattered path (bin + IDW p=2, r=12 m, of the recorded nodes);
+    MAE / RMSE against the truth with holes excluded and counted, and the
+    kernel time of each fill.  The oracle's time of each fill is added at 5 %."""
+    import torch
+    from gen import grid_b_case
+    stream = torch.cuda.current_stream()
+    log(f"grid B: sampling the {n_fine}^2 truth")
+    base = grid_b_case(n_fine, 0.0)
+    out = {"workload": f"{n_fine}^2 fractal seafloor at 4 m, every other node recorded, "
+                       "random removal of recorded nodes; fills: bilinear, Catmull-Rom, "
+                       "kriging (range 24 m) from the recorded grid, IDW p=2 r=12 m from "
+                       "the recorded nodes", "cases": []}
+    for frac in (0.01, 0.05, 0.1):
+        c = grid_b_case(n_fine, frac, truth=base["truth"])
+        cs, ts = c["coarse_spec"], c["truth_spec"]
+        coarse = torch.from_numpy(c["coarse"]).to(dev)
+        fine = torch.empty((ts.ny, ts.nx), dtype=torch.float32, device=dev)
+        rm = 3.0 * cs.dx
+        radius = 3.0 * ts.dx
+        grid = ag.auv_grid_create(ts)
+        x, y, z = (torch.from_numpy(c[k]).to(dev) for k in ("x", "y", "z"))
+        ws = torch.empty(ag.auv_bin_workspace_size(grid, int(x.numel()), radius, 0),
+                         dtype=torch.uint8, device=dev)
+        params = ag.idw_params(2.0, radius, 1, 0)
+
+        def idw():
+            bins = ag.auv_bin_points(grid, x, y, z, radius, 0, ws=ws, stream=stream)
+            ag.auv_interp_idw(grid, bins, params, fine, None, None, None, stream=stream)
+
+        fns = {
+            "bilinear": lambda: ag.auv_resample_bilinear(coarse, cs, fine, ts, stream=stream),
+            "bicubic": lambda: ag.auv_resample_bicubic(coarse, cs, fine, ts, stream=stream),
+            "kriging": lambda: ag.auv_resample_kriging(coarse, cs, fine, ts, rm, stream=stream),
+            "idw": idw,
+        }
+        case = {"removal": frac, "recorded": int(x.numel()),
+                "interpolated": int(c["interp"].sum()), "methods": {}}
+        for m, fn in fns.items():
+            ms = _median_ms(fn, stream, 20)
+            fn()
+            torch.cuda.synchronize()
+            r = _fill_metrics(fine.cpu().numpy(), c["truth"], c["interp"])
+            r["gpu_ms"] = round(ms, 5)
+            case["methods"][m] = r
+        if with_cpu and frac == 0.05:
+            for m, ms in cpu_grid_b(c, rm, radius).items():
+                case["methods"][m]["cpu_ms"] = ms
+        out["cases"].append(case)
+        log(f"grid B {frac}: " + "; ".join(
+            f"{m} mae={r['mae']} rmse={r['rmse']} holes={r['holes']} {r['gpu_ms']} ms"
+            for m, r in case["methods"].items()))
+        ag.auv_grid_destroy(grid)
+    return out
+
+
+def cpu_grid_b(c, range_m, radius):
+    """Oracle leg of the grid-B protocol: each fill once, in ms."""
+    import oracle
+    oracle.build(force=False)
+    th = host_threads()
+    cs, ts = c["coarse_spec"], c["truth_spec"]
+    oc = oracle.Grid(cs.x0, cs.y0, cs.dx, cs.dy, cs.nx, cs.ny)
+    ot = oracle.Grid(ts.x0, ts.y0, ts.dx, ts.dy, ts.nx, ts.ny)
+    src = c["coarse"].astype("float64")
+    out = {}
+    for m in RESAMPLERS + ("idw",):
+        c0 = time.perf_counter()
+        if m == "kriging":
+            oracle.kriging(oc, src, ot, range_m, nthreads=th)
+        elif m == "idw":
+            oracle.idw(ot, c["x"], c["y"], c["z"], radius, 2.0, 1, 0, bin_log2=19, nthreads=th)
+        else:
+            getattr(oracle, m)(oc, src, ot, nthreads=th)
+        out[m] = round((time.perf_counter() - c0) * 1e3, 3)
+    return out
+
+
 def precision_report(ag, dev):
     """The same swath at UTM-scale coordinates (easting 5e5, northing 4e6): each
     precision variant of the IDW against the FP64 oracle, plus its kernel time."""
@@ -302,6 +464,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the 16-vehicle serving replay (FIFO vs continuous batching)")
     ap.add_argument("--serving-seconds", type=float, default=3.0)
+    ap.add_argument("--no-grids", action="store_true",
+                    help="skip the grid-A sweep and the grid-B infill protocol")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -454,6 +618,11 @@ def main():
     if not args.no_serving:
         serving = serving_report(ag, dev, duration=args.serving_seconds)
 
+    grid_a = grid_b = None
+    if not args.no_grids:
+        grid_a = grid_a_sweep(ag, dev, with_cpu=not args.no_cpu_baseline)
+        grid_b = grid_b_report(ag, dev, with_cpu=not args.no_cpu_baseline)
+
     value = nodes / (ms_per_step * 1e-3)
     rec = {
         "metric": METRIC, "value": round(value, 1), "unit": "grid nodes/s", "n_gpus": 1,
@@ -474,6 +643,8 @@ def main():
         "kriging": kriging,
         "batched_tiles": batched,
         "serving": serving,
+        "grid_a_sweep": grid_a,
+        "grid_b_infill": grid_b,
     }
     print(json.dumps(rec), flush=True)
 

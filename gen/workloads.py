@@ -1,8 +1,7 @@
 """Seeded synthetic workloads (numpy only).
 
-Every generator is deterministic in its seed.  The recipes follow the workload
-descriptions in DESIGN.md ("Input recipe"); the paper's own GEBCO grids are not
-available, so a seeded fractal seafloor stands in for real bathymetry.
+Every generator is deterministic in its seed.  The paper's own GEBCO grids are
+not available, so a seeded fractal seafloor stands in for real bathymetry.
 """
 from __future__ import annotations
 
@@ -281,3 +280,75 @@ def serving_schedule(n_vehicles=16, duration=60.0, rate_hz=20.0, n_lo=2000,
     if max_requests is not None:
         reqs = reqs[:max_requests]
     return grids, reqs
+
+
+# ------------------------------------------------- grid-to-grid protocols --
+
+def dem_on_grid(g: GridSpec, seed: int = 5) -> np.ndarray:
+    """Elevation -D(x, y) of the fractal seafloor at the node centres of g,
+    float64 [ny, nx]."""
+    xs = g.x0 + (np.arange(g.nx) + 0.5) * g.dx
+    ys = g.y0 + (np.arange(g.ny) + 0.5) * g.dy
+    X, Y = np.meshgrid(xs, ys)
+    return -seafloor_depth(X, Y, seed=seed)
+
+
+def grid_a_case(points: int, h: float = 1.0, seed: int = 11, patch: int = 1024):
+    """Row infill (Sec. V, grid A): a complete source grid and a destination
+    grid whose rows lie midway between successive source rows, with about
+    `points` destination nodes (nx ~ sqrt(points), ny = ceil(points / nx)).
+    Sources larger than patch x patch repeat one DEM patch of that size
+    (sampling the DEM node by node would take minutes at 1e8 nodes).
+    Returns (src_spec, src float32 [ny+1, nx], dst_spec)."""
+    nx = max(2, int(round(points ** 0.5)))
+    ny = max(1, -(-points // nx))
+    src = GridSpec(0.0, 0.0, h, h, nx, ny + 1)
+    dst = GridSpec(0.0, 0.5 * h, h, h, nx, ny)
+    pw, ph = min(nx, patch), min(ny + 1, patch)
+    v = dem_on_grid(GridSpec(0.0, 0.0, h, h, pw, ph), seed).astype(np.float32)
+    if (pw, ph) != (nx, ny + 1):
+        v = np.tile(v, (-(-(ny + 1) // ph), -(-nx // pw)))[: ny + 1, :nx]
+    return src, np.ascontiguousarray(v), dst
+
+
+def grid_b_case(n_fine: int = 2048, frac: float = 0.05, h: float = 4.0, seed: int = 13,
+                truth=None):
+    """Random-removal infill (Sec. V, grid B) on the fractal seafloor.
+
+    The truth is the DEM on a fine n_fine^2 grid at spacing h.  The recorded
+    grid holds every other fine node (spacing 2h, its origin shifted by -h/2 so
+    that coarse node (a, b) sits on fine node (2a, 2b)); round(frac * m) of its
+    m nodes, drawn without replacement, are removed (NaN).  The interpolated
+    points are every fine node whose value was not recorded.
+
+    Returns a dict: truth_spec, truth (float64), coarse_spec, coarse (float32
+    with NaN), removed (bool, coarse shape), interp (bool, fine shape) and
+    x, y, z (float64) of the recorded nodes, for the scattered path.  A truth
+    from an earlier call with the same n_fine, h and seed may be passed in to
+    skip recomputing the DEM."""
+    if n_fine % 2:
+        raise ValueError("n_fine must be even")
+    rng = np.random.default_rng(seed * 1000 + int(round(frac * 1e4)))
+    tspec = GridSpec(0.0, 0.0, h, h, n_fine, n_fine)
+    if truth is None:
+        truth = dem_on_grid(tspec, seed)
+    elif truth.shape != (n_fine, n_fine):
+        raise ValueError("truth does not match n_fine")
+    nc = n_fine // 2
+    cspec = GridSpec(-0.5 * h, -0.5 * h, 2.0 * h, 2.0 * h, nc, nc)
+    coarse = truth[::2, ::2].copy()
+    m = nc * nc
+    k = int(round(frac * m))
+    removed = np.zeros(m, dtype=bool)
+    removed[rng.choice(m, size=k, replace=False)] = True
+    removed = removed.reshape(nc, nc)
+    coarse[removed] = np.nan
+    interp = np.ones((n_fine, n_fine), dtype=bool)
+    interp[::2, ::2] = removed
+    a, b = np.nonzero(~removed)
+    x = cspec.x0 + (b + 0.5) * cspec.dx
+    y = cspec.y0 + (a + 0.5) * cspec.dy
+    return {"truth_spec": tspec, "truth": truth, "coarse_spec": cspec,
+            "coarse": coarse.astype(np.float32), "removed": removed, "interp": interp,
+            "x": x.astype(np.float64), "y": y.astype(np.float64),
+            "z": coarse[~removed].astype(np.float64)}

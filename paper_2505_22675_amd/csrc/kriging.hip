@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 
 namespace auv {
 
@@ -227,6 +228,43 @@ bool kriging_inverse(double dx, double dy, double range, double *out)
     return true;
 }
 
+// The last few inverses, keyed by (dx, dy, range): a resample loop over
+// tiles of one survey pays the elimination once.
+struct KrigCache {
+    std::mutex mu;
+    struct Entry {
+        double dx, dy, range;
+        double kinv[26 * 26];
+    } e[8];
+    int used = 0, next = 0;
+};
+
+bool cached_inverse(double dx, double dy, double range, double *out)
+{
+    static KrigCache cache;
+    {
+        std::lock_guard<std::mutex> lk(cache.mu);
+        for (int i = 0; i < cache.used; ++i) {
+            const KrigCache::Entry &e = cache.e[i];
+            if (e.dx == dx && e.dy == dy && e.range == range) {
+                std::memcpy(out, e.kinv, sizeof(e.kinv));
+                return true;
+            }
+        }
+    }
+    if (!kriging_inverse(dx, dy, range, out))
+        return false;
+    std::lock_guard<std::mutex> lk(cache.mu);
+    KrigCache::Entry &e = cache.e[cache.next];
+    e.dx = dx;
+    e.dy = dy;
+    e.range = range;
+    std::memcpy(e.kinv, out, sizeof(e.kinv));
+    cache.next = (cache.next + 1) % 8;
+    cache.used = std::min(cache.used + 1, 8);
+    return true;
+}
+
 }  // namespace
 
 auv_status launch_kriging(const float *src, const auv_grid_desc &s, float *dst,
@@ -257,7 +295,7 @@ auv_status launch_kriging(const float *src, const auv_grid_desc &s, float *dst,
     const double l = 1.4426950408889634 / range;
     p.c2 = (float)(l * l);
     double kinv[26 * 26];
-    if (!kriging_inverse(s.dx, s.dy, range, kinv))
+    if (!cached_inverse(s.dx, s.dy, range, kinv))
         return fail(AUV_ERR_INVALID, "singular kriging system for this spacing and range");
     for (int j = 0; j < 26; ++j)
         for (int q = 0; q < 25; ++q)
