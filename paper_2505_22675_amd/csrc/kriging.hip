@@ -8,14 +8,21 @@
 //     [ 1' 0 ] [   mu   ] = [ 1 ]
 // with G the variogram between the 25 nodes, g the variogram between each node
 // and the destination point and gamma(h) = 1 - exp(-h / a) (the sill cancels
-// from the weights).  G depends only on the node spacing and the range, not
-// on where the window sits, so the 26 x 26 matrix is inverted once on the
-// host (FP64, Gauss-Jordan with partial pivoting) and each node costs a
-// matrix-vector product.  Written as
-//     z = z_c + sum_j g_j w_j,   w = K^-T (z - z_c, 0)
-// (z_c: the window centre), w depends only on the window, so a thread walking
-// down a column computes it once per window and each node adds one 26-term
-// product.  A window with a non-finite value falls back to bilinear.
+// from the weights).  K = [G 1; 1' 0] depends only on the node spacing and the
+// range, not on where the window sits, so it is inverted once on the host
+// (FP64, Gauss-Jordan with partial pivoting) and, written as
+//     z = z_c + sum_j g_j w_j,   w = K^-1 (z - z_c, 0)
+// (z_c: the window centre; K is symmetric), w depends only on the window: a
+// thread walking down a column computes it once per window and each node adds
+// one 26-term product.
+//
+// K commutes with the mirror images of the window in x and in y, so in the
+// basis of sums and differences of mirrored nodes (per axis: a0+a4, a1+a3,
+// a2 | a0-a4, a1-a3) its inverse is block diagonal, with blocks for the four
+// parity classes (even/odd in y, even/odd in x) of 10 (with the unbiasedness
+// row), 6, 6 and 4 rows: w costs 178 multiply-adds and two 40-add transforms
+// instead of 650 multiply-adds.  A window with a non-finite value falls back to
+// bilinear.
 #include "resample_axis.hpp"
 
 #include <algorithm>
@@ -31,6 +38,7 @@ namespace {
 constexpr int kKrigCols = 256;    // destination columns per block (one per thread)
 constexpr int kKrigRows = 8;      // destination rows per block
 constexpr int kKrigStage = 6144;  // source values staged in LDS
+constexpr int kBlockFloats = 10 * 9 + 6 * 6 + 6 * 6 + 4 * 4;
 
 struct KrigArgs {
     const float *src;
@@ -40,9 +48,11 @@ struct KrigArgs {
     int snx, sny, dnx, dny;
     float fdx, fdy;  // source spacing
     float c2;        // (log2(e) / range)^2
-    // rows 0..24 and 25 of the inverse kriging matrix restricted to its first
-    // 25 columns, transposed: kt[j * 25 + q] = Kinv[q][j]
-    float kt[26 * 25];
+    // the diagonal blocks of K^-1 in the mirror basis, row-major: even-even
+    // 10 x 9 (rows: 9 nodes and the unbiasedness entry; its column is never
+    // used since the data vector has a zero there), even-odd 6 x 6, odd-even
+    // 6 x 6, odd-odd 4 x 4
+    float mb[kBlockFloats];
 };
 
 using cfloat = const __attribute__((address_space(4))) float;
@@ -137,21 +147,95 @@ __global__ __launch_bounds__(kKrigCols) void k_kriging(const KrigArgs p)
                 bad |= !isfinite(z);
                 dz[q] = z - zc;
             }
-            // the matrix is read from the argument segment through scalar
-            // loads here, once per window: an opaque pointer keeps the 650
-            // values from being held in registers across the row loop
-            cfloat *kt = (cfloat *)((const __attribute__((address_space(4))) char *)
-                                        __builtin_amdgcn_kernarg_segment_ptr() +
-                                    offsetof(KrigArgs, kt));
-            asm volatile("" : "+s"(kt));
+            // mirror transform per row (x), then per column (y):
+            // component order per axis: sums 0+4, 1+3, 2 | differences 0-4, 1-3
+            float t[25];
 #pragma unroll
-            for (int j = 0; j < 26; ++j) {
+            for (int k = 0; k < 5; ++k) {
+                const float *d = &dz[k * 5];
+                t[k * 5 + 0] = d[0] + d[4];
+                t[k * 5 + 1] = d[1] + d[3];
+                t[k * 5 + 2] = d[2];
+                t[k * 5 + 3] = d[0] - d[4];
+                t[k * 5 + 4] = d[1] - d[3];
+            }
+            float sv[25];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) {
+                sv[0 * 5 + i] = t[0 * 5 + i] + t[4 * 5 + i];
+                sv[1 * 5 + i] = t[1 * 5 + i] + t[3 * 5 + i];
+                sv[2 * 5 + i] = t[2 * 5 + i];
+                sv[3 * 5 + i] = t[0 * 5 + i] - t[4 * 5 + i];
+                sv[4 * 5 + i] = t[1 * 5 + i] - t[3 * 5 + i];
+            }
+            // the blocks are read from the argument segment through scalar
+            // loads here, once per window: an opaque pointer keeps the 178
+            // values from being held in registers across the row loop
+            cfloat *mb = (cfloat *)((const __attribute__((address_space(4))) char *)
+                                        __builtin_amdgcn_kernarg_segment_ptr() +
+                                    offsetof(KrigArgs, mb));
+            asm volatile("" : "+s"(mb));
+            float uv[25];
+            float u25;
+            // even-even: y components 0..2, x components 0..2, then the
+            // unbiasedness row
+#pragma unroll
+            for (int r = 0; r < 10; ++r) {
                 float acc = 0.0f;
 #pragma unroll
-                for (int q = 0; q < 25; ++q)
-                    acc = fmaf(kt[j * 25 + q], dz[q], acc);
-                w[j] = acc;
+                for (int c = 0; c < 9; ++c)
+                    acc = fmaf(mb[r * 9 + c], sv[(c / 3) * 5 + c % 3], acc);
+                if (r < 9)
+                    uv[(r / 3) * 5 + r % 3] = acc;
+                else
+                    u25 = acc;
             }
+            // even-odd: y 0..2, x 3..4
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 6; ++c)
+                    acc = fmaf(mb[90 + r * 6 + c], sv[(c / 2) * 5 + 3 + c % 2], acc);
+                uv[(r / 2) * 5 + 3 + r % 2] = acc;
+            }
+            // odd-even: y 3..4, x 0..2
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 6; ++c)
+                    acc = fmaf(mb[126 + r * 6 + c], sv[(3 + c / 3) * 5 + c % 3], acc);
+                uv[(3 + r / 3) * 5 + r % 3] = acc;
+            }
+            // odd-odd: y 3..4, x 3..4
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc = fmaf(mb[162 + r * 4 + c], sv[(3 + c / 2) * 5 + 3 + c % 2], acc);
+                uv[(3 + r / 2) * 5 + 3 + r % 2] = acc;
+            }
+            // back to nodes: transpose of the mirror transform, y then x
+#pragma unroll
+            for (int i = 0; i < 5; ++i) {
+                t[0 * 5 + i] = uv[0 * 5 + i] + uv[3 * 5 + i];
+                t[4 * 5 + i] = uv[0 * 5 + i] - uv[3 * 5 + i];
+                t[1 * 5 + i] = uv[1 * 5 + i] + uv[4 * 5 + i];
+                t[3 * 5 + i] = uv[1 * 5 + i] - uv[4 * 5 + i];
+                t[2 * 5 + i] = uv[2 * 5 + i];
+            }
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const float *y = &t[k * 5];
+                w[k * 5 + 0] = y[0] + y[3];
+                w[k * 5 + 4] = y[0] - y[3];
+                w[k * 5 + 1] = y[1] + y[4];
+                w[k * 5 + 3] = y[1] - y[4];
+                w[k * 5 + 2] = y[2];
+            }
+            w[25] = u25;
             cur = wy;
         }
         float v;
@@ -228,6 +312,80 @@ bool kriging_inverse(double dx, double dy, double range, double *out)
     return true;
 }
 
+// M = D^-1 T K^-1 T' D^-1 for the mirror transform T (per axis: rows
+// a0+a4, a1+a3, a2, a0-a4, a1-a3; the unbiasedness entry kept) and D = T T',
+// so that K^-1 = T' M T.  M is block diagonal over the parity classes; its
+// blocks are packed as the kernel reads them.  Fails if an entry outside the
+// blocks is not negligible (it is zero in exact arithmetic).
+bool mirror_blocks(const double *kinv, float *out)
+{
+    static const double ax[5][5] = {{1, 0, 0, 0, 1},
+                                    {0, 1, 0, 1, 0},
+                                    {0, 0, 1, 0, 0},
+                                    {1, 0, 0, 0, -1},
+                                    {0, 1, 0, -1, 0}};
+    static const double dax[5] = {2, 2, 1, 2, 2};
+    double T[26][26] = {}, Dinv[26];
+    for (int ky = 0; ky < 5; ++ky)
+        for (int kx = 0; kx < 5; ++kx) {
+            for (int k = 0; k < 5; ++k)
+                for (int i = 0; i < 5; ++i)
+                    T[ky * 5 + kx][k * 5 + i] = ax[ky][k] * ax[kx][i];
+            Dinv[ky * 5 + kx] = 1.0 / (dax[ky] * dax[kx]);
+        }
+    T[25][25] = 1.0;
+    Dinv[25] = 1.0;
+    double A[26][26], M[26][26];  // A = K^-1 T'
+    for (int r = 0; r < 26; ++r)
+        for (int c = 0; c < 26; ++c) {
+            double acc = 0.0;
+            for (int k = 0; k < 26; ++k)
+                acc += kinv[r * 26 + k] * T[c][k];
+            A[r][c] = acc;
+        }
+    double big = 0.0;
+    for (int r = 0; r < 26; ++r)
+        for (int c = 0; c < 26; ++c) {
+            double acc = 0.0;
+            for (int k = 0; k < 26; ++k)
+                acc += T[r][k] * A[k][c];
+            M[r][c] = Dinv[r] * acc * Dinv[c];
+            big = std::max(big, std::fabs(M[r][c]));
+        }
+    // parity class of a mirror-basis index: 0 even-even, 1 even-odd,
+    // 2 odd-even, 3 odd-odd (the unbiasedness entry is even-even)
+    auto cls = [](int q) { return q == 25 ? 0 : 2 * (q / 5 >= 3) + (q % 5 >= 3); };
+    for (int r = 0; r < 26; ++r)
+        for (int c = 0; c < 26; ++c)
+            if (cls(r) != cls(c) && !(std::fabs(M[r][c]) <= 1e-9 * big))
+                return false;
+    // members of each class in the kernel's order
+    int ee[10], eo[6], oe[6], oo[4];
+    for (int r = 0; r < 9; ++r)
+        ee[r] = (r / 3) * 5 + r % 3;
+    ee[9] = 25;
+    for (int r = 0; r < 6; ++r) {
+        eo[r] = (r / 2) * 5 + 3 + r % 2;
+        oe[r] = (3 + r / 3) * 5 + r % 3;
+    }
+    for (int r = 0; r < 4; ++r)
+        oo[r] = (3 + r / 2) * 5 + 3 + r % 2;
+    int o = 0;
+    for (int r = 0; r < 10; ++r)
+        for (int c = 0; c < 9; ++c)
+            out[o++] = (float)M[ee[r]][ee[c]];
+    for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c)
+            out[o++] = (float)M[eo[r]][eo[c]];
+    for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c)
+            out[o++] = (float)M[oe[r]][oe[c]];
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c)
+            out[o++] = (float)M[oo[r]][oo[c]];
+    return o == kBlockFloats;
+}
+
 // The last few inverses, keyed by (dx, dy, range): a resample loop over
 // tiles of one survey pays the elimination once.
 struct KrigCache {
@@ -297,9 +455,8 @@ auv_status launch_kriging(const float *src, const auv_grid_desc &s, float *dst,
     double kinv[26 * 26];
     if (!cached_inverse(s.dx, s.dy, range, kinv))
         return fail(AUV_ERR_INVALID, "singular kriging system for this spacing and range");
-    for (int j = 0; j < 26; ++j)
-        for (int q = 0; q < 25; ++q)
-            p.kt[j * 25 + q] = (float)kinv[q * 26 + j];
+    if (!mirror_blocks(kinv, p.mb))
+        return fail(AUV_ERR_INVALID, "kriging inverse lost its mirror symmetry (range far outside the node spacing)");
     const dim3 grid((unsigned)((d.nx + kKrigCols - 1) / kKrigCols),
                     (unsigned)((d.ny + kKrigRows - 1) / kKrigRows));
     k_kriging<<<grid, kKrigCols, 0, st>>>(p);
