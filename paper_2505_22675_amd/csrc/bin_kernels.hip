@@ -529,6 +529,13 @@ constexpr int kSmallRank = 64;     // largest bin ranked member by member
 constexpr int kRowLds = 8192;      // keys of a row ranked in LDS (as u32 indices)
 constexpr int kRowSortLds = kRowLds / 2;  // keys of a row bitonic-sorted in LDS (u64)
 constexpr int kRowU = 8;           // keys per thread per pass: loads kept in flight
+// rows of up to kThreads * kStageU keys are ranked in registers and written
+// out through two LDS arrays of that length, carved from the u64 key area
+constexpr int kStageU = 12;
+static_assert(2 * kThreads * kStageU * sizeof(int32_t) <=
+                  kRowSortLds * sizeof(unsigned long long),
+              "row staging does not fit the key area");
+static_assert(kThreads * kStageU <= kRowLds, "staged rows must take the LDS ranking");
 
 // for (k = threadIdx.x; k < n; k += kThreads) f(k, keys[r0 + k]), with kRowU
 // key loads issued before any is used
@@ -607,6 +614,72 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
             s_i[p] = (uint32_t)key;
         });
         __syncthreads();
+        if (n <= kThreads * kStageU) {
+            // one pass: ranks and gathers in registers, then the records are
+            // placed at their sorted slots in LDS (the index list is dead by
+            // then) and written out contiguously, two arrays at a time
+            const int k0 = threadIdx.x;
+            uint32_t ix[kStageU];
+            int pos[kStageU];
+            int4 rr[kStageU];
+#pragma unroll
+            for (int j = 0; j < kStageU; ++j) {
+                const int k = k0 + j * kThreads;
+                const unsigned long long key = k < n ? keys[r0 + k] : 0ull;
+                ix[j] = (uint32_t)key;
+                pos[j] = k < n ? (int)(key >> 32) : -1;  // bin column until ranked
+            }
+#pragma unroll
+            for (int j = 0; j < kStageU; ++j) {
+                if (pos[j] >= 0) {
+                    const int bx = pos[j];
+                    const int b0 = bx == 0 ? 0 : s_h[bx - 1], b1 = s_h[bx];
+                    int rank = 0;
+                    for (int q = b0; q < b1; ++q)
+                        rank += s_i[q] < ix[j] ? 1 : 0;
+                    pos[j] = b0 + rank;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kStageU; ++j)
+                if (pos[j] >= 0)
+                    rr[j] = rec[ix[j]];
+            int32_t *s_a = reinterpret_cast<int32_t *>(s_k);
+            int32_t *s_b = s_a + kThreads * kStageU;
+            __syncthreads();  // every rank is read: the index list is free
+#pragma unroll
+            for (int j = 0; j < kStageU; ++j)
+                if (pos[j] >= 0) {
+                    s_a[pos[j]] = rr[j].x;
+                    s_b[pos[j]] = rr[j].y;
+                }
+            __syncthreads();
+            for (int k = threadIdx.x; k < n; k += kThreads) {
+                o.X[r0 + k] = s_a[k];
+                o.Y[r0 + k] = s_b[k];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kStageU; ++j)
+                if (pos[j] >= 0) {
+                    s_a[pos[j]] = rr[j].z;
+                    s_b[pos[j]] = rr[j].w;
+                }
+            __syncthreads();
+            for (int k = threadIdx.x; k < n; k += kThreads) {
+                o.res[r0 + k] = (uint32_t)s_a[k];
+                o.z[r0 + k] = __int_as_float(s_b[k]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kStageU; ++j)
+                if (pos[j] >= 0)
+                    s_a[pos[j]] = (int)ix[j];
+            __syncthreads();
+            for (int k = threadIdx.x; k < n; k += kThreads)
+                o.idx[r0 + k] = s_a[k];
+            return;
+        }
         // ranks first (LDS), then the kRowU record gathers in flight together
         for (int k0 = threadIdx.x; k0 < n; k0 += kThreads * kRowU) {
             unsigned long long kk[kRowU];
