@@ -214,8 +214,12 @@ auv_status auv_resample_bicubic(const float *src, const auv_grid_desc *s,
  * row included); z = sum of weights x depths.  A neighbourhood with a
  * non-finite value, or a source grid under 5 x 5, falls back to the bilinear
  * value (a hole when one of its corners is NaN).  FP32 arithmetic on depths
- * relative to the window centre.  Errors as auv_resample_bilinear, plus
- * AUV_ERR_INVALID for a non-positive range. */
+ * relative to the window centre; from a range of 16 hypot(dx, dy) on,
+ * 1 - exp(-h / range) is taken from its Taylor series (every h / range is then
+ * at most 1/4), which keeps the FP32 result to about 1e-6 relative however
+ * long the range.  Errors as auv_resample_bilinear, plus AUV_ERR_INVALID for
+ * a non-positive or non-finite range and AUV_ERR_RANGE for a range above 1e4
+ * source spacings. */
 auv_status auv_resample_kriging(const float *src, const auv_grid_desc *s,
                                 float *dst, const auv_grid_desc *d, double range,
                                 auv_stream stream);

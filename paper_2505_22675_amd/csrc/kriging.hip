@@ -39,6 +39,7 @@ constexpr int kKrigCols = 256;    // destination columns per block (one per thre
 constexpr int kKrigRows = 8;      // destination rows per block
 constexpr int kKrigStage = 6144;  // source values staged in LDS
 constexpr int kBlockFloats = 10 * 9 + 6 * 6 + 6 * 6 + 4 * 4;
+constexpr double kMaxRangeSpacings = 1e4;  // the FP64 inverse stays well conditioned
 
 struct KrigArgs {
     const float *src;
@@ -47,7 +48,7 @@ struct KrigArgs {
     double dx0, dy0, ddx, ddy;
     int snx, sny, dnx, dny;
     float fdx, fdy;  // source spacing
-    float c2;        // (log2(e) / range)^2
+    float c2;        // (log2(e) / range)^2, or (1 / range)^2 for the series form
     // the diagonal blocks of K^-1 in the mirror basis, row-major: even-even
     // 10 x 9 (rows: 9 nodes and the unbiasedness entry; its column is never
     // used since the data vector has a zero there), even-odd 6 x 6, odd-even
@@ -69,6 +70,16 @@ __device__ inline int window_start(double u, int n)
 // w = K^-1 (z - z_c, 0), sum_q w_q = 0, so with g_q = 1 - e_q,
 // e_q = exp(-h_q / range):
 //     z = z_c + sum_q g_q w_q + w_25 = z_c + w_25 - sum_q e_q w_q.
+// The entries of A grow with range / spacing while g shrinks, so the FP32
+// rounding of e_q (about 6e-8 near 1) times w_q grows with the range: the
+// exp form is kept to ranges under 16 hypot(dx, dy) (22.6 spacings on a
+// square grid; relative depth error of a few 1e-6).  A window node lies at
+// most 4 spacings per axis from the destination point (2.5 inside the grid,
+// 4 where the window is moved in at an edge), so from there on every t =
+// h / range is at most 1/4 and kSeries evaluates g_q = 1 - exp(-t) by its
+// Taylor series to t^7 (truncation under 2e-9 relative), whose rounding is
+// relative to g_q itself, and sums z = z_c + w_25 + sum_q g_q w_q.
+template <bool kSeries>
 __global__ __launch_bounds__(kKrigCols) void k_kriging(const KrigArgs p)
 {
     __shared__ int s_wx[kKrigCols], s_i0[kKrigCols], s_i1[kKrigCols];
@@ -257,11 +268,22 @@ __global__ __launch_bounds__(kKrigCols) void k_kriging(const KrigArgs p)
                 const float ey2 = e * e * p.c2;
 #pragma unroll
                 for (int i = 0; i < 5; ++i) {
-                    const float h = __builtin_amdgcn_sqrtf(ex2[i] + ey2);
-                    acc = fmaf(__builtin_amdgcn_exp2f(-h), w[k * 5 + i], acc);
+                    const float t = __builtin_amdgcn_sqrtf(ex2[i] + ey2);
+                    if constexpr (kSeries) {
+                        // 1 - exp(-t) = t (1 - t/2 (1 - t/3 (... (1 - t/7))))
+                        float g = fmaf(-t, 1.0f / 7.0f, 1.0f);
+                        g = fmaf(-t * (1.0f / 6.0f), g, 1.0f);
+                        g = fmaf(-t * (1.0f / 5.0f), g, 1.0f);
+                        g = fmaf(-t * (1.0f / 4.0f), g, 1.0f);
+                        g = fmaf(-t * (1.0f / 3.0f), g, 1.0f);
+                        g = fmaf(-t * 0.5f, g, 1.0f);
+                        acc = fmaf(t * g, w[k * 5 + i], acc);
+                    } else {
+                        acc = fmaf(__builtin_amdgcn_exp2f(-t), w[k * 5 + i], acc);
+                    }
                 }
             }
-            v = zc + (w[25] - acc);
+            v = kSeries ? zc + (w[25] + acc) : zc + (w[25] - acc);
         }
         p.dst[(int64_t)(row0 + r) * p.dnx + col0 + c] = v;
     }
@@ -276,7 +298,7 @@ bool kriging_inverse(double dx, double dy, double range, double *out)
     for (int pi = 0; pi < 25; ++pi) {
         for (int qi = 0; qi < 25; ++qi) {
             const double h = std::hypot((pi % 5 - qi % 5) * dx, (pi / 5 - qi / 5) * dy);
-            A[pi][qi] = 1.0 - std::exp(-h / range);
+            A[pi][qi] = -std::expm1(-h / range);
         }
         A[pi][25] = 1.0;
         A[25][pi] = 1.0;
@@ -450,7 +472,13 @@ auv_status launch_kriging(const float *src, const auv_grid_desc &s, float *dst,
     p.dny = d.ny;
     p.fdx = (float)s.dx;
     p.fdy = (float)s.dy;
-    const double l = 1.4426950408889634 / range;
+    // a window node lies at most 4 spacings per axis from the destination
+    // point (the point is clamped into the grid, the window moved in at edges)
+    const double hmax = 4.0 * std::hypot(s.dx, s.dy);
+    const bool series = hmax / range <= 0.25;
+    if (range > kMaxRangeSpacings * std::max(s.dx, s.dy))
+        return fail(AUV_ERR_RANGE, "kriging range above 1e4 source spacings");
+    const double l = (series ? 1.0 : 1.4426950408889634) / range;
     p.c2 = (float)(l * l);
     double kinv[26 * 26];
     if (!cached_inverse(s.dx, s.dy, range, kinv))
@@ -459,7 +487,10 @@ auv_status launch_kriging(const float *src, const auv_grid_desc &s, float *dst,
         return fail(AUV_ERR_INVALID, "kriging inverse lost its mirror symmetry (range far outside the node spacing)");
     const dim3 grid((unsigned)((d.nx + kKrigCols - 1) / kKrigCols),
                     (unsigned)((d.ny + kKrigRows - 1) / kKrigRows));
-    k_kriging<<<grid, kKrigCols, 0, st>>>(p);
+    if (series)
+        k_kriging<true><<<grid, kKrigCols, 0, st>>>(p);
+    else
+        k_kriging<false><<<grid, kKrigCols, 0, st>>>(p);
     AUV_HIP(hipGetLastError());
     return AUV_OK;
 }

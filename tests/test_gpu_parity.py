@@ -475,6 +475,10 @@ def test_idw_dense_form_parity(ag, orc, kcap, power, min_pts, snap, bin_log2):
     ((40, 40), (160, 160), 10.0, 0.02),  # holes: windows with NaN fall back to bilinear
     ((5, 5), (13, 11), 2.0, 0.0),        # the smallest grid with a 5 x 5 window
     ((9, 600), (9, 1300), 1.0, 0.0),     # wide and flat: many column blocks
+    ((30, 40), (90, 70), 20.0, 0.0),     # longest range of the exp form
+    ((30, 40), (90, 70), 60.0, 0.0),     # series form of 1 - exp(-t)
+    ((24, 24), (61, 47), 1000.0, 0.01),  # very long range, holes
+    ((12, 12), (20, 20), 9000.0, 0.0),   # near the range limit
 ])
 def test_kriging_parity(ag, orc, src_shape, dst_shape, range_cells, nan_frac):
     sh, sw = src_shape
@@ -520,7 +524,7 @@ def test_kriging_rejects_bad_range(ag):
     g = GridSpec(0.0, 0.0, 1.0, 1.0, 8, 8)
     src = torch.zeros((8, 8), dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    for r in (0.0, -1.0, float("nan"), float("inf")):
+    for r in (0.0, -1.0, float("nan"), float("inf"), 2e4):
         with pytest.raises(ag.AuvError):
             ag.auv_resample_kriging(src, g, dst, g, r)
 
