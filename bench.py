@@ -479,9 +479,8 @@ def main():
         print(json.dumps({"copy_bytes": a.numel() * 4}))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: "
-              "this build runs on a single GPU (the path would shard by spatial tile "
-              "with an r-halo)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path would shard by spatial tile with an r-halo)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -7,8 +7,8 @@
  * the HIP library: every definition below is written out here on its own.
  *
  * Definitions followed (the paper, "Towards Real-Time Interpolation for
- * Enhanced AUV Deep Sea Mapping", has no IDW; the IDW/NN readings are listed in
- * DESIGN.md under "Readings"):
+ * Enhanced AUV Deep Sea Mapping", has no IDW; the IDW/NN readings are stated
+ * where each function is defined, in auv_oracle.c):
  *   - bilinear: Sec. III-A, the four-corner weighted average;
  *   - NaN samples are invalid candidates: Sec. III-B and III-D;
  *   - holes (no fallback for bilinear): Sec. III-D and V-D (Kerguelen);
