@@ -29,6 +29,20 @@ constexpr int kBilCols = kBilThreads * 4;  // destination columns per block
 constexpr int kBilRows = 8;                // destination rows per block
 constexpr int kBilStage = 6144;            // source values staged in LDS
 
+// Patch of a block in a 1-D launch of ncb x nrb patches (row-major: column
+// band fastest).  Blocks are dealt round-robin to the 8 XCDs; each XCD takes
+// a contiguous run of patches, so it writes whole destination rows instead of
+// one column band of every row.
+__device__ inline void patch_of(int ncb, int nrb, int *bx, int *by)
+{
+    const int total = ncb * nrb;
+    const int b = (int)blockIdx.x;
+    const int xcd = b & 7, q = total >> 3, rem = total & 7;
+    const int t = xcd * q + min(xcd, rem) + (b >> 3);
+    *bx = t % ncb;
+    *by = t / ncb;
+}
+
 // One block owns a 1024-column x 8-row patch of the destination.  The FP64
 // axis maps of its columns and rows are computed once into LDS; the source
 // rectangle the patch reads is staged into LDS with coalesced loads when it
@@ -41,8 +55,10 @@ __global__ __launch_bounds__(kBilThreads) void k_bilinear(BilArgs p)
     __shared__ int s_j0[kBilRows], s_j1[kBilRows];
     __shared__ float s_s[kBilRows];
     __shared__ float s_src[kBilStage];
-    const int col0 = blockIdx.x * kBilCols;
-    const int row0 = blockIdx.y * kBilRows;
+    int pbx, pby;
+    patch_of((p.dnx + kBilCols - 1) / kBilCols, (p.dny + kBilRows - 1) / kBilRows, &pbx, &pby);
+    const int col0 = pbx * kBilCols;
+    const int row0 = pby * kBilRows;
     const int ncol = min(kBilCols, p.dnx - col0);
     const int nrow = min(kBilRows, p.dny - row0);
     for (int c = threadIdx.x; c < kBilCols; c += kBilThreads) {
@@ -151,8 +167,10 @@ __global__ __launch_bounds__(kBilThreads) void k_bicubic(BilArgs p)
     __shared__ int s_j0[kBilRows];
     __shared__ float s_s[kBilRows];
     __shared__ float s_src[kCubStage];
-    const int col0 = blockIdx.x * kBilCols;
-    const int row0 = blockIdx.y * kBilRows;
+    int pbx, pby;
+    patch_of((p.dnx + kBilCols - 1) / kBilCols, (p.dny + kBilRows - 1) / kBilRows, &pbx, &pby);
+    const int col0 = pbx * kBilCols;
+    const int row0 = pby * kBilRows;
     const int ncol = min(kBilCols, p.dnx - col0);
     const int nrow = min(kBilRows, p.dny - row0);
     for (int c = threadIdx.x; c < kBilCols; c += kBilThreads) {
@@ -277,8 +295,8 @@ auv_status launch_bicubic(const float *src, const auv_grid_desc &s, float *dst,
     p.sny = s.ny;
     p.dnx = d.nx;
     p.dny = d.ny;
-    const dim3 grid((unsigned)((d.nx + kBilCols - 1) / kBilCols),
-                    (unsigned)((d.ny + kBilRows - 1) / kBilRows));
+    const unsigned grid = (unsigned)(((d.nx + kBilCols - 1) / kBilCols) *
+                                     ((d.ny + kBilRows - 1) / kBilRows));
     k_bicubic<<<grid, kBilThreads, 0, st>>>(p);
     AUV_HIP(hipGetLastError());
     return AUV_OK;
@@ -302,8 +320,8 @@ auv_status launch_bilinear(const float *src, const auv_grid_desc &s, float *dst,
     p.sny = s.ny;
     p.dnx = d.nx;
     p.dny = d.ny;
-    const dim3 grid((unsigned)((d.nx + kBilCols - 1) / kBilCols),
-                    (unsigned)((d.ny + kBilRows - 1) / kBilRows));
+    const unsigned grid = (unsigned)(((d.nx + kBilCols - 1) / kBilCols) *
+                                     ((d.ny + kBilRows - 1) / kBilRows));
     k_bilinear<<<grid, kBilThreads, 0, st>>>(p);
     AUV_HIP(hipGetLastError());
     return AUV_OK;
