@@ -81,10 +81,7 @@ __global__ __launch_bounds__(kBilThreads) void k_bilinear(BilArgs p)
     const int sw = ih - il + 1, sh = jh - jl + 1;
     const bool staged = (long long)sw * sh <= kBilStage;
     if (staged) {
-        for (int e = threadIdx.x; e < sw * sh; e += kBilThreads) {
-            const int r = e / sw, c = e - r * sw;
-            s_src[e] = p.src[(int64_t)(jl + r) * p.snx + il + c];
-        }
+        stage_rect(p.src, p.snx, jl, il, sw, sh, s_src, kBilThreads);
         __syncthreads();
     }
     const int c = threadIdx.x * 4;
@@ -192,10 +189,7 @@ __global__ __launch_bounds__(kBilThreads) void k_bicubic(BilArgs p)
     const int sw = ih - il + 1, sh = jh - jl + 1;
     const bool staged = (long long)sw * sh <= kCubStage;
     if (staged) {
-        for (int e = threadIdx.x; e < sw * sh; e += kBilThreads) {
-            const int r = e / sw, c = e - r * sw;
-            s_src[e] = p.src[(int64_t)(jl + r) * p.snx + il + c];
-        }
+        stage_rect(p.src, p.snx, jl, il, sw, sh, s_src, kBilThreads);
         __syncthreads();
     }
     const int c = threadIdx.x * 4;

@@ -119,10 +119,7 @@ __global__ __launch_bounds__(kKrigCols) void k_kriging(const KrigArgs p)
     const int sw = ih - il + 1, sh = jh - jl + 1;
     const bool staged = (long long)sw * sh <= kKrigStage;
     if (staged) {
-        for (int e = threadIdx.x; e < sw * sh; e += kKrigCols) {
-            const int r = e / sw, c = e - r * sw;
-            s_src[e] = p.src[(int64_t)(jl + r) * p.snx + il + c];
-        }
+        stage_rect(p.src, p.snx, jl, il, sw, sh, s_src, kKrigCols);
         __syncthreads();
     }
     const int c = threadIdx.x;

@@ -32,4 +32,30 @@ __device__ inline Axis axis_of(double x0d, double dd, int j, double x0s, double 
     return a;
 }
 
+// Copy the source rectangle [jl, jl + sh) x [il, il + sw) into s_dst
+// (row-major, pitch sw) with nthreads threads: element e = t + k nthreads
+// walks (row, column) incrementally, one division per thread in all.
+__device__ inline void stage_rect(const float *__restrict__ src, int snx, int jl, int il,
+                                  int sw, int sh, float *s_dst, int nthreads)
+{
+    const int t = (int)threadIdx.x;
+    const int n = sw * sh;
+    if (t >= n)
+        return;
+    int r = t / sw, c = t - r * sw;
+    const int dr = nthreads / sw, dc = nthreads - dr * sw;
+    const float *row = src + (int64_t)(jl + r) * snx + il;
+    for (int e = t; e < n; e += nthreads) {
+        s_dst[e] = row[c];
+        c += dc;
+        int step = dr;
+        if (c >= sw) {
+            c -= sw;
+            ++step;
+        }
+        r += step;
+        row += (int64_t)step * snx;
+    }
+}
+
 }  // namespace auv
