@@ -39,6 +39,8 @@ def host_threads() -> int:
 KERNEL_SOURCES = {
     "k_idw_window": ["idw_window_impl.hpp", "idw_window.hip", "auv_internal.hpp"],
     "k_bilinear": ["bilinear_kernels.hip", "resample_axis.hpp", "auv_internal.hpp"],
+    "k_kriging": ["kriging.hip", "resample_axis.hpp", "auv_internal.hpp"],
+    "k_bicubic": ["bilinear_kernels.hip", "resample_axis.hpp", "auv_internal.hpp"],
 }
 
 
@@ -53,6 +55,26 @@ def kernel_source_digest(kernel: str) -> str:
             h.update(fn.encode())
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4   # wave64 VALU instructions per second (16-lane SIMDs)
+
+
+def valu_from_profile(kernel: str):
+    """VALU wave instructions per launch of `kernel` from the committed
+    rocprofv3 SQ summary; None when there is none or the sources changed."""
+    path = os.path.join(ROOT, "profiles", "valu_issue_swath2M.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("valu_instr "):
+                _, name, val, digest = line.split()
+                rec[name] = (int(val), digest)
+    if kernel not in rec or rec[kernel][1] != kernel_source_digest(kernel):
+        return None
+    return rec[kernel][0]
 
 
 def traffic_from_profile(kernel: str):
@@ -559,6 +581,13 @@ def main():
                 "avg_launch_ms": round(float(dur[dom]), 5)}
 
     roofline["traffic"] = traffic_from_profile(kernel_names[dom])
+    # the kernel is bound by VALU issue, not bytes: its profiled instruction
+    # count over the live launch time against the chip's issue rate
+    valu = valu_from_profile(kernel_names[dom])
+    roofline["valu_issue"] = None if valu is None else {
+        "instructions": valu, "achieved_per_s": round(valu / (dur[dom] * 1e-3), 1),
+        "peak_per_s": VALU_ISSUE_PEAK,
+        "frac": round(valu / (dur[dom] * 1e-3) / VALU_ISSUE_PEAK, 4)}
 
     # next row: Catmull-Rom 2x of the same grid (not part of the step)
     cub = torch.empty_like(up)
@@ -599,6 +628,10 @@ def main():
                "nodes_per_s": round(up.numel() / (krig_ms * 1e-3), 1),
                "achieved_GBs": round(krig_gbs, 1), "hbm_frac": round(krig_gbs / HBM_PEAK_GBS, 4),
                "nan_nodes": int(torch.isnan(krig).sum().item())}
+    kv = valu_from_profile("k_kriging")
+    kriging["valu_issue"] = None if kv is None else {
+        "instructions": kv, "achieved_per_s": round(kv / (krig_ms * 1e-3), 1),
+        "peak_per_s": VALU_ISSUE_PEAK, "frac": round(kv / (krig_ms * 1e-3) / VALU_ISSUE_PEAK, 4)}
     log(f"kriging 2x: {krig_ms:.4f} ms ({krig_gbs:.0f} GB/s)")
 
     cpu = None
