@@ -320,6 +320,7 @@ constexpr int kRowChunk = 1024;          // soundings per block in k_row_hist
 constexpr int kRowPerThread = kRowChunk / kThreads;
 constexpr int kMaxRowsLds = 8192;        // bin rows in the LDS histogram
 constexpr int kScatterPer = 4;           // soundings per thread in k_row_scatter
+constexpr int kRunsMax = 8;              // row runs per wave for the grouped reservation
 
 __device__ void row_hist_block(const RowItem &it, int blk, int *s_cnt)
 {
@@ -369,9 +370,20 @@ __device__ void row_hist_block(const RowItem &it, int blk, int *s_cnt)
         }
         // Reserve slots in the block's row counters, one LDS atomic per
         // distinct row in the wave (a ping's beams share a bin row, so
-        // per-lane atomics would serialise on one address).
+        // per-lane atomics would serialise on one address) -- unless the
+        // wave's rows change more than kRunsMax times (soundings in no
+        // particular order): then one LDS atomic per lane, on mostly
+        // distinct addresses.  Positions inside a row are arbitrary either
+        // way; the row sort orders every row by (bin, original index).
         const int rj = row[j];
+        const int rprev = __shfl_up(rj, 1, 64);
+        const int runs = __popcll(__ballot(rj >= 0 && (lane_id() == 0 || rprev != rj)));
         unsigned long long pending = __ballot(rj >= 0);
+        if (runs > kRunsMax) {
+            if (rj >= 0)
+                lr[j] = atomicAdd(&s_cnt[rj], 1);
+            pending = 0ull;
+        }
         while (pending) {
             const int leader = __ffsll((long long)pending) - 1;
             const int r = __shfl(rj, leader, 64);

@@ -479,6 +479,8 @@ def test_idw_dense_form_parity(ag, orc, kcap, power, min_pts, snap, bin_log2):
     ((30, 40), (90, 70), 60.0, 0.0),     # series form of 1 - exp(-t)
     ((24, 24), (61, 47), 1000.0, 0.01),  # very long range, holes
     ((12, 12), (20, 20), 9000.0, 0.0),   # near the range limit
+    ((5, 40), (11, 90), 2.0, 0.0),       # exactly five rows: every window the same rows
+    ((40, 5), (70, 9), 2.0, 0.05),       # exactly five columns, holes
 ])
 def test_kriging_parity(ag, orc, src_shape, dst_shape, range_cells, nan_frac):
     sh, sw = src_shape
