@@ -12,6 +12,7 @@ Prints ONE JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -439,6 +440,10 @@ def serving_report(ag, dev, duration=3.0, stress=10.0):
             for v in range(len(grids)):      # admit every vehicle, load the kernels
                 sess.submit(v, empty, empty, empty)
             sess.drain()
+            # no collector pauses inside the replay: latency runs from each
+            # request's scheduled arrival, so a stalled submit loop would count
+            gc.collect()
+            gc.disable()
             t0 = sess.now() + 0.05
             tickets = []
             for r in reqs:
@@ -451,6 +456,7 @@ def serving_report(ag, dev, duration=3.0, stress=10.0):
                         time.sleep(d - 1e-3)
                 tickets.append(sess.submit(r.vehicle, r.x, r.y, r.z, t_arrival=ta))
             sess.drain()
+            gc.enable()
             infos = [sess.poll(t) for t in tickets]
             lat = np.array([i.t_done - i.t_arrival for i in infos]) * 1e3
             queue = np.array([i.t_launch - i.t_arrival for i in infos]) * 1e3

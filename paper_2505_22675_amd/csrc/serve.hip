@@ -18,6 +18,7 @@
 #include "idw_window_impl.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -376,6 +377,9 @@ struct auv_session {
     bool failed = false;
     std::string error;
     std::thread worker;
+    // requests queued so far; read by the worker without the lock while it
+    // waits for a launch to finish
+    std::atomic<uint64_t> n_queued{0};
 
     double now() const
     {
@@ -661,8 +665,18 @@ void worker_main(auv_session *s)
             continue;
         }
         if (!s->inflight.empty()) {
+            // wait for the oldest launch without the session lock, so that
+            // submits and polls never queue behind the worker; leave early
+            // when a request arrives that a free launch could take
+            const hipEvent_t ev = s->inflight.front().ev;
+            const bool room = s->inflight.size() < max_inflight;
+            const uint64_t seen = s->n_queued.load(std::memory_order_acquire);
             lk.unlock();
-            std::this_thread::yield();
+            while (hipEventQuery(ev) == hipErrorNotReady) {
+                if (room && s->n_queued.load(std::memory_order_acquire) != seen)
+                    break;
+                std::this_thread::yield();
+            }
             lk.lock();
             continue;
         }
@@ -819,6 +833,7 @@ auv_status auv_session_submit(auv_session *s, int32_t vehicle, const double *x, 
         s->tickets.push_back(tk);
         const uint64_t id = s->tickets.size();
         s->pending.push_back(Pick{id, vehicle, slot, n});
+        s->n_queued.fetch_add(1, std::memory_order_release);
         *ticket = id;
     }
     s->cv_work.notify_one();
