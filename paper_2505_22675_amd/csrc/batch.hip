@@ -89,9 +89,9 @@ __global__ __launch_bounds__(64) void k_idw_batch_window(const IdwItem *__restri
     __shared__ float s_emax[win::kAcc];
     __shared__ int s_beg[win::kMaxRows];
     __shared__ int s_off[win::kMaxRows + 1];
-    __shared__ int4 s_r0[64], s_r1[64];
+    __shared__ int4 s_rec[128];
     const win::WinSmem sm{s_nd, s_cnt, s_key, nullptr, nullptr, nullptr, s_emax, s_beg, s_off,
-                          s_r0, s_r1, nullptr};
+                          s_rec, s_rec + 1, nullptr};
     const int home = blockIdx.x & (kQueues - 1);
     for (int k = 0; k < kQueues; ++k) {
         const int q = (home + k) & (kQueues - 1);

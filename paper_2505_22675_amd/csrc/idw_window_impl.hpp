@@ -457,8 +457,10 @@ struct WinSmem {
     float *bz;                  // best depth                    [kAcc] (unpacked)
     float *emax;                // running log2 weight max       [kAcc] (general p)
     int *beg, *off;             // staging rows                  [kMaxRows(+1)]
-    int4 *r0;                   // kept soundings: ia, jb, 8 qb, 4 qb          [64]
-    int4 *r1;                   //   residual x, y, depth - zref (bits), index  [64]
+    int4 *r0;                   // kept soundings: ia, jb, 8 qb, 4 qb          [64, stride 2]
+    int4 *r1;                   //   residual x, y, depth - zref (bits), index  [64, stride 2]
+                                // (r1 = r0 + 1: a record's halves are adjacent, so both
+                                //  reads of a visit share one LDS address)
     float2 *rv;                 //   variant coordinates; depth  [64] (variants, unpacked)
 };
 
@@ -617,8 +619,8 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                 const int slot = __builtin_amdgcn_mbcnt_hi(
                     (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
                 const int qb = pia * kRS + pjb;
-                sm.r0[slot] = make_int4(pia, pjb, qb * 8, qb * 4);
-                sm.r1[slot] = make_int4(__float_as_int(prx), __float_as_int(pry),
+                sm.r0[2 * slot] = make_int4(pia, pjb, qb * 8, qb * 4);
+                sm.r1[2 * slot] = make_int4(__float_as_int(prx), __float_as_int(pry),
                                         __float_as_int(pdz), pidx);
                 if constexpr (!kExact)
                     sm.rv[slot] = make_float2(pvx, pvy);
@@ -627,16 +629,22 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
             }
             // the records are read back by the same wave, in order
             __builtin_amdgcn_wave_barrier();
-            const int4 *rp0 = sm.r0;
-            const int4 *rp1 = sm.r1;
+            // the record address lives in a VGPR (LDS reads take one) and
+            // both halves are read from it with an immediate offset
+            typedef int v4i __attribute__((ext_vector_type(4)));
+            typedef __attribute__((address_space(3))) const v4i lds_v4i;
+            lds_v4i *rp0 = (lds_v4i *)sm.r0;
+            asm volatile("" : "+v"(rp0));
             const float2 *rpv = sm.rv;
             while (m) {
                 const int l = __ffsll((long long)m) - 1;
                 m &= m - 1ull;
                 const int sx = sext23(__builtin_amdgcn_readlane(px, l));
                 const int sy = sext23(__builtin_amdgcn_readlane(py, l));
-                const int4 w0 = *rp0++;
-                const int4 w1 = *rp1++;
+                const v4i v0 = rp0[0], v1 = rp0[1];
+                rp0 += 2;
+                const int4 w0 = make_int4(v0.x, v0.y, v0.z, v0.w);
+                const int4 w1 = make_int4(v1.x, v1.y, v1.z, v1.w);
                 const int ia = w0.x, jb = w0.y, qb8 = w0.z, qb4 = w0.w;
                 const float srx = __int_as_float(w1.x), sry = __int_as_float(w1.y);
                 const float sdz = __int_as_float(w1.z);
@@ -839,10 +847,10 @@ __global__ __launch_bounds__(64) void k_idw_window(auv_bin_view bv, IdwArgs a, W
     __shared__ float s_emax[kPmode == 0 ? kAcc : 1];
     __shared__ int s_beg[kMaxRows];
     __shared__ int s_off[kMaxRows + 1];
-    __shared__ int4 s_r0[64], s_r1[64];
+    __shared__ int4 s_rec[128];
     __shared__ float2 s_rv[kPrec == AUV_P_FP32_REBASE && kPacked ? 1 : 64];
     const WinSmem sm{s_nd, s_cnt, s_key, s_bd2, s_bidx, s_bz, s_emax, s_beg, s_off,
-                     s_r0, s_r1, s_rv};
+                     s_rec, s_rec + 1, s_rv};
     window_tile<kMode, kPmode, kPacked, kChunks, kPrec>(
         bv, a, g, xcd_tile(blockIdx.x, ntx * nty), ntx, sm);
 }

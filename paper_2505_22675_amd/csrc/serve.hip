@@ -135,12 +135,12 @@ __global__ __launch_bounds__(64 * kServeParts) void k_serve_update(
     __shared__ float s_emax[1];
     __shared__ int s_beg[kServeParts][win::kMaxRows];
     __shared__ int s_off[kServeParts][win::kMaxRows + 1];
-    __shared__ int4 s_r0[kServeParts][64], s_r1[kServeParts][64];
+    __shared__ int4 s_rec[kServeParts][128];
     __shared__ float s_zref[kServeParts];
     __shared__ int s_task;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const win::WinSmem sm{s_nd[wave], s_cnt[wave], nullptr, nullptr, nullptr, nullptr, s_emax,
-                          s_beg[wave], s_off[wave], s_r0[wave], s_r1[wave], nullptr};
+                          s_beg[wave], s_off[wave], s_rec[wave], s_rec[wave] + 1, nullptr};
     int t0x = 0, t0y = 0, tcols = 1, nt = 0;
     if (lane < count) {
         const ServeItem &it = items[lane];
