@@ -148,6 +148,94 @@ __device__ inline float catmull_rom(float p0, float p1, float p2, float p3, floa
 
 constexpr int kCubStage = 6144;  // source values staged in LDS (with a one-tap halo)
 
+// The row walk of k_bicubic for one thread's four columns: taps from the
+// staged rectangle (kStaged) or from the source grid in global memory.
+template <bool kStaged>
+__device__ __forceinline__ void bicubic_walk(const BilArgs &p, const float *s_src,
+                                             const int *s_i0, const float *s_t,
+                                             const int *s_j0, const float *s_s, int il, int jl,
+                                             int sw, int c, int ncol, int nrow, int row0,
+                                             int col0)
+{
+    auto src_row = [&](int jr) -> const float * {
+        if constexpr (kStaged)
+            return s_src + (jr - jl) * sw;
+        else
+            return p.src + (int64_t)jr * p.snx;
+    };
+    // tap columns (relative to the staged rectangle, or absolute) per node
+    int tc[4][4];
+    float t[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i0 = s_i0[min(c + k, ncol - 1)];
+        t[k] = s_t[min(c + k, ncol - 1)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            tc[k][q] = min(max(i0 - 1 + q, 0), p.snx - 1) - (kStaged ? il : 0);
+    }
+    // horizontal cubics of source row jr at this thread's 4 columns
+    auto hrow = [&](int jr) {
+        const float *row = src_row(jr);
+        float4 h;
+        h.x = catmull_rom(row[tc[0][0]], row[tc[0][1]], row[tc[0][2]], row[tc[0][3]], t[0]);
+        h.y = catmull_rom(row[tc[1][0]], row[tc[1][1]], row[tc[1][2]], row[tc[1][3]], t[1]);
+        h.z = catmull_rom(row[tc[2][0]], row[tc[2][1]], row[tc[2][2]], row[tc[2][3]], t[2]);
+        h.w = catmull_rom(row[tc[3][0]], row[tc[3][1]], row[tc[3][2]], row[tc[3][3]], t[3]);
+        return h;
+    };
+    auto clampr = [&](int j) { return min(max(j, 0), p.sny - 1); };
+    float4 h0 = make_float4(0.f, 0.f, 0.f, 0.f), h1 = h0, h2 = h0, h3 = h0;
+    int cur = INT_MIN;  // j0 of the rows held in h0..h3 (block-uniform)
+    const bool vec = c + 4 <= ncol && (p.dnx & 3) == 0 &&
+                     (reinterpret_cast<uintptr_t>(p.dst) & 15) == 0;
+    for (int r = 0; r < nrow; ++r) {
+        const float s = s_s[r];
+        const int j0 = s_j0[r];
+        if (j0 != cur) {
+            if (j0 == cur + 1) {
+                h0 = h1;
+                h1 = h2;
+                h2 = h3;
+                h3 = hrow(clampr(j0 + 2));
+            } else {
+                h0 = hrow(clampr(j0 - 1));
+                h1 = hrow(clampr(j0));
+                h2 = hrow(clampr(j0 + 1));
+                h3 = hrow(clampr(j0 + 2));
+            }
+            cur = j0;
+        }
+        float v[4];
+        v[0] = catmull_rom(h0.x, h1.x, h2.x, h3.x, s);
+        v[1] = catmull_rom(h0.y, h1.y, h2.y, h3.y, s);
+        v[2] = catmull_rom(h0.z, h1.z, h2.z, h3.z, s);
+        v[3] = catmull_rom(h0.w, h1.w, h2.w, h3.w, s);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!isfinite(v[k])) {
+                // bilinear on the inner taps (the corners of the node's cell)
+                const float *r1 = src_row(clampr(j0));
+                const float *r2 = src_row(clampr(j0 + 1));
+                const float q00 = r1[tc[k][1]], q10 = r1[tc[k][2]];
+                const float q01 = r2[tc[k][1]], q11 = r2[tc[k][2]];
+                const float top = q00 + t[k] * (q10 - q00);
+                const float bot = q01 + t[k] * (q11 - q01);
+                v[k] = top + s * (bot - top);
+            }
+        }
+        float *outp = p.dst + (int64_t)(row0 + r) * p.dnx + col0 + c;
+        if (vec) {
+            typedef float f4v __attribute__((ext_vector_type(4)));
+            const f4v vv = {v[0], v[1], v[2], v[3]};
+            __builtin_nontemporal_store(vv, reinterpret_cast<f4v *>(outp));
+        } else {
+            for (int k = 0; k < 4 && c + k < ncol; ++k)
+                outp[k] = v[k];
+        }
+    }
+}
+
 // Catmull-Rom resample, the same patch layout as k_bilinear.  Taps are the
 // source indices i0 - 1 .. i0 + 2 (clamped to the grid) around each node's
 // cell; the cubic runs along x on the 4 tap rows, then along y.  The cubic is
@@ -195,78 +283,12 @@ __global__ __launch_bounds__(kBilThreads) void k_bicubic(BilArgs p)
     const int c = threadIdx.x * 4;
     if (c >= ncol)
         return;
-    // tap columns (relative to the staged rectangle, or absolute) per node
-    int tc[4][4];
-    float t[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int i0 = s_i0[min(c + k, ncol - 1)];
-        t[k] = s_t[min(c + k, ncol - 1)];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            tc[k][q] = min(max(i0 - 1 + q, 0), p.snx - 1) - (staged ? il : 0);
-    }
-    // horizontal cubics of source row jr at this thread's 4 columns
-    auto hrow = [&](int jr) {
-        const float *row = staged ? s_src + (jr - jl) * sw : p.src + (int64_t)jr * p.snx;
-        float4 h;
-        h.x = catmull_rom(row[tc[0][0]], row[tc[0][1]], row[tc[0][2]], row[tc[0][3]], t[0]);
-        h.y = catmull_rom(row[tc[1][0]], row[tc[1][1]], row[tc[1][2]], row[tc[1][3]], t[1]);
-        h.z = catmull_rom(row[tc[2][0]], row[tc[2][1]], row[tc[2][2]], row[tc[2][3]], t[2]);
-        h.w = catmull_rom(row[tc[3][0]], row[tc[3][1]], row[tc[3][2]], row[tc[3][3]], t[3]);
-        return h;
-    };
-    auto clampr = [&](int j) { return min(max(j, 0), p.sny - 1); };
-    float4 h0 = make_float4(0.f, 0.f, 0.f, 0.f), h1 = h0, h2 = h0, h3 = h0;
-    int cur = INT_MIN;  // j0 of the rows held in h0..h3 (block-uniform)
-    const bool vec = c + 4 <= ncol && (p.dnx & 3) == 0 &&
-                     (reinterpret_cast<uintptr_t>(p.dst) & 15) == 0;
-    for (int r = 0; r < nrow; ++r) {
-        const float s = s_s[r];
-        const int j0 = s_j0[r];
-        if (j0 != cur) {
-            if (j0 == cur + 1) {
-                h0 = h1;
-                h1 = h2;
-                h2 = h3;
-                h3 = hrow(clampr(j0 + 2));
-            } else {
-                h0 = hrow(clampr(j0 - 1));
-                h1 = hrow(clampr(j0));
-                h2 = hrow(clampr(j0 + 1));
-                h3 = hrow(clampr(j0 + 2));
-            }
-            cur = j0;
-        }
-        float v[4];
-        v[0] = catmull_rom(h0.x, h1.x, h2.x, h3.x, s);
-        v[1] = catmull_rom(h0.y, h1.y, h2.y, h3.y, s);
-        v[2] = catmull_rom(h0.z, h1.z, h2.z, h3.z, s);
-        v[3] = catmull_rom(h0.w, h1.w, h2.w, h3.w, s);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (!isfinite(v[k])) {
-                // bilinear on the inner taps (the corners of the node's cell)
-                const int ja = clampr(j0), jb = clampr(j0 + 1);
-                const float *r1 = staged ? s_src + (ja - jl) * sw : p.src + (int64_t)ja * p.snx;
-                const float *r2 = staged ? s_src + (jb - jl) * sw : p.src + (int64_t)jb * p.snx;
-                const float q00 = r1[tc[k][1]], q10 = r1[tc[k][2]];
-                const float q01 = r2[tc[k][1]], q11 = r2[tc[k][2]];
-                const float top = q00 + t[k] * (q10 - q00);
-                const float bot = q01 + t[k] * (q11 - q01);
-                v[k] = top + s * (bot - top);
-            }
-        }
-        float *outp = p.dst + (int64_t)(row0 + r) * p.dnx + col0 + c;
-        if (vec) {
-            typedef float f4v __attribute__((ext_vector_type(4)));
-            const f4v vv = {v[0], v[1], v[2], v[3]};
-            __builtin_nontemporal_store(vv, reinterpret_cast<f4v *>(outp));
-        } else {
-            for (int k = 0; k < 4 && c + k < ncol; ++k)
-                outp[k] = v[k];
-        }
-    }
+    // separate instantiations keep LDS and global reads apart (a pointer that
+    // may be either would make every tap a flat load)
+    if (staged)
+        bicubic_walk<true>(p, s_src, s_i0, s_t, s_j0, s_s, il, jl, sw, c, ncol, nrow, row0, col0);
+    else
+        bicubic_walk<false>(p, s_src, s_i0, s_t, s_j0, s_s, il, jl, sw, c, ncol, nrow, row0, col0);
 }
 
 }  // namespace
