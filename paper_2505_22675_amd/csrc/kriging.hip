@@ -30,6 +30,7 @@
 #include <cstddef>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 
 namespace auv {
 
@@ -125,165 +126,177 @@ __global__ __launch_bounds__(kKrigCols) void k_kriging(const KrigArgs p)
     const int c = threadIdx.x;
     if (c >= ncol)
         return;
-    auto at = [&](int j, int i) {  // source value at row j, column i
-        return staged ? s_src[(j - jl) * sw + (i - il)] : p.src[(int64_t)j * p.snx + i];
-    };
-    const int wx = s_wx[c];
-    // squared x offsets to the window columns, scaled by (log2(e) / range)^2
-    float ex2[5];
-    {
-        const float du = s_du[c];
-#pragma unroll
-        for (int i = 0; i < 5; ++i) {
-            const float e = ((float)i - du) * p.fdx;
-            ex2[i] = e * e * p.c2;
-        }
-    }
-    float w[26];
-    float zc = 0.0f;
-    bool bad = false;
-    int cur = -1;  // window row start of w (the same for every thread of the block)
-    for (int r = 0; r < nrow; ++r) {
-        const int wy = s_wy[r];
-        if (wy != cur) {
-            float dz[25];
-            zc = at(wy + 2, wx + 2);
-            bad = false;
-#pragma unroll
-            for (int q = 0; q < 25; ++q) {
-                const float z = at(wy + q / 5, wx + q % 5);
-                bad |= !isfinite(z);
-                dz[q] = z - zc;
-            }
-            // mirror transform per row (x), then per column (y):
-            // component order per axis: sums 0+4, 1+3, 2 | differences 0-4, 1-3
-            float t[25];
-#pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                const float *d = &dz[k * 5];
-                t[k * 5 + 0] = d[0] + d[4];
-                t[k * 5 + 1] = d[1] + d[3];
-                t[k * 5 + 2] = d[2];
-                t[k * 5 + 3] = d[0] - d[4];
-                t[k * 5 + 4] = d[1] - d[3];
-            }
-            float sv[25];
-#pragma unroll
+    // separate instantiations keep LDS and global reads apart (a value that
+    // may come from either would make every read a flat load)
+    auto walk = [&](auto staged_t) {
+        constexpr bool kStaged = decltype(staged_t)::value;
+        auto at = [&](int j, int i) {  // source value at row j, column i
+            if constexpr (kStaged)
+                return s_src[(j - jl) * sw + (i - il)];
+            else
+                return p.src[(int64_t)j * p.snx + i];
+        };
+        const int wx = s_wx[c];
+        // squared x offsets to the window columns, scaled by (log2(e) / range)^2
+        float ex2[5];
+        {
+            const float du = s_du[c];
+    #pragma unroll
             for (int i = 0; i < 5; ++i) {
-                sv[0 * 5 + i] = t[0 * 5 + i] + t[4 * 5 + i];
-                sv[1 * 5 + i] = t[1 * 5 + i] + t[3 * 5 + i];
-                sv[2 * 5 + i] = t[2 * 5 + i];
-                sv[3 * 5 + i] = t[0 * 5 + i] - t[4 * 5 + i];
-                sv[4 * 5 + i] = t[1 * 5 + i] - t[3 * 5 + i];
+                const float e = ((float)i - du) * p.fdx;
+                ex2[i] = e * e * p.c2;
             }
-            // the blocks are read from the argument segment through scalar
-            // loads here, once per window: an opaque pointer keeps the 178
-            // values from being held in registers across the row loop
-            cfloat *mb = (cfloat *)((const __attribute__((address_space(4))) char *)
-                                        __builtin_amdgcn_kernarg_segment_ptr() +
-                                    offsetof(KrigArgs, mb));
-            asm volatile("" : "+s"(mb));
-            float uv[25];
-            float u25;
-            // even-even: y components 0..2, x components 0..2, then the
-            // unbiasedness row
-#pragma unroll
-            for (int r = 0; r < 10; ++r) {
-                float acc = 0.0f;
-#pragma unroll
-                for (int c = 0; c < 9; ++c)
-                    acc = fmaf(mb[r * 9 + c], sv[(c / 3) * 5 + c % 3], acc);
-                if (r < 9)
-                    uv[(r / 3) * 5 + r % 3] = acc;
-                else
-                    u25 = acc;
-            }
-            // even-odd: y 0..2, x 3..4
-#pragma unroll
-            for (int r = 0; r < 6; ++r) {
-                float acc = 0.0f;
-#pragma unroll
-                for (int c = 0; c < 6; ++c)
-                    acc = fmaf(mb[90 + r * 6 + c], sv[(c / 2) * 5 + 3 + c % 2], acc);
-                uv[(r / 2) * 5 + 3 + r % 2] = acc;
-            }
-            // odd-even: y 3..4, x 0..2
-#pragma unroll
-            for (int r = 0; r < 6; ++r) {
-                float acc = 0.0f;
-#pragma unroll
-                for (int c = 0; c < 6; ++c)
-                    acc = fmaf(mb[126 + r * 6 + c], sv[(3 + c / 3) * 5 + c % 3], acc);
-                uv[(3 + r / 3) * 5 + r % 3] = acc;
-            }
-            // odd-odd: y 3..4, x 3..4
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float acc = 0.0f;
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    acc = fmaf(mb[162 + r * 4 + c], sv[(3 + c / 2) * 5 + 3 + c % 2], acc);
-                uv[(3 + r / 2) * 5 + 3 + r % 2] = acc;
-            }
-            // back to nodes: transpose of the mirror transform, y then x
-#pragma unroll
-            for (int i = 0; i < 5; ++i) {
-                t[0 * 5 + i] = uv[0 * 5 + i] + uv[3 * 5 + i];
-                t[4 * 5 + i] = uv[0 * 5 + i] - uv[3 * 5 + i];
-                t[1 * 5 + i] = uv[1 * 5 + i] + uv[4 * 5 + i];
-                t[3 * 5 + i] = uv[1 * 5 + i] - uv[4 * 5 + i];
-                t[2 * 5 + i] = uv[2 * 5 + i];
-            }
-#pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                const float *y = &t[k * 5];
-                w[k * 5 + 0] = y[0] + y[3];
-                w[k * 5 + 4] = y[0] - y[3];
-                w[k * 5 + 1] = y[1] + y[4];
-                w[k * 5 + 3] = y[1] - y[4];
-                w[k * 5 + 2] = y[2];
-            }
-            w[25] = u25;
-            cur = wy;
         }
-        float v;
-        if (bad) {
-            // a non-finite neighbour: bilinear on the node's cell corners
-            const int i0 = s_i0[c], i1 = s_i1[c], j0 = s_j0[r], j1 = s_j1[r];
-            const float t = s_t[c], s = s_s[r];
-            const float q00 = at(j0, i0), q10 = at(j0, i1);
-            const float q01 = at(j1, i0), q11 = at(j1, i1);
-            const float top = q00 + t * (q10 - q00);
-            const float bot = q01 + t * (q11 - q01);
-            v = top + s * (bot - top);
-        } else {
-            const float dv = s_dv[r];
-            float acc = 0.0f;
-#pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                const float e = ((float)k - dv) * p.fdy;
-                const float ey2 = e * e * p.c2;
-#pragma unroll
+        float w[26];
+        float zc = 0.0f;
+        bool bad = false;
+        int cur = -1;  // window row start of w (the same for every thread of the block)
+        for (int r = 0; r < nrow; ++r) {
+            const int wy = s_wy[r];
+            if (wy != cur) {
+                float dz[25];
+                zc = at(wy + 2, wx + 2);
+                bad = false;
+    #pragma unroll
+                for (int q = 0; q < 25; ++q) {
+                    const float z = at(wy + q / 5, wx + q % 5);
+                    bad |= !isfinite(z);
+                    dz[q] = z - zc;
+                }
+                // mirror transform per row (x), then per column (y):
+                // component order per axis: sums 0+4, 1+3, 2 | differences 0-4, 1-3
+                float t[25];
+    #pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    const float *d = &dz[k * 5];
+                    t[k * 5 + 0] = d[0] + d[4];
+                    t[k * 5 + 1] = d[1] + d[3];
+                    t[k * 5 + 2] = d[2];
+                    t[k * 5 + 3] = d[0] - d[4];
+                    t[k * 5 + 4] = d[1] - d[3];
+                }
+                float sv[25];
+    #pragma unroll
                 for (int i = 0; i < 5; ++i) {
-                    const float t = __builtin_amdgcn_sqrtf(ex2[i] + ey2);
-                    if constexpr (kSeries) {
-                        // 1 - exp(-t) = t (1 - t/2 (1 - t/3 (... (1 - t/7))))
-                        float g = fmaf(-t, 1.0f / 7.0f, 1.0f);
-                        g = fmaf(-t * (1.0f / 6.0f), g, 1.0f);
-                        g = fmaf(-t * (1.0f / 5.0f), g, 1.0f);
-                        g = fmaf(-t * (1.0f / 4.0f), g, 1.0f);
-                        g = fmaf(-t * (1.0f / 3.0f), g, 1.0f);
-                        g = fmaf(-t * 0.5f, g, 1.0f);
-                        acc = fmaf(t * g, w[k * 5 + i], acc);
-                    } else {
-                        acc = fmaf(__builtin_amdgcn_exp2f(-t), w[k * 5 + i], acc);
+                    sv[0 * 5 + i] = t[0 * 5 + i] + t[4 * 5 + i];
+                    sv[1 * 5 + i] = t[1 * 5 + i] + t[3 * 5 + i];
+                    sv[2 * 5 + i] = t[2 * 5 + i];
+                    sv[3 * 5 + i] = t[0 * 5 + i] - t[4 * 5 + i];
+                    sv[4 * 5 + i] = t[1 * 5 + i] - t[3 * 5 + i];
+                }
+                // the blocks are read from the argument segment through scalar
+                // loads here, once per window: an opaque pointer keeps the 178
+                // values from being held in registers across the row loop
+                cfloat *mb = (cfloat *)((const __attribute__((address_space(4))) char *)
+                                            __builtin_amdgcn_kernarg_segment_ptr() +
+                                        offsetof(KrigArgs, mb));
+                asm volatile("" : "+s"(mb));
+                float uv[25];
+                float u25;
+                // even-even: y components 0..2, x components 0..2, then the
+                // unbiasedness row
+    #pragma unroll
+                for (int r = 0; r < 10; ++r) {
+                    float acc = 0.0f;
+    #pragma unroll
+                    for (int c = 0; c < 9; ++c)
+                        acc = fmaf(mb[r * 9 + c], sv[(c / 3) * 5 + c % 3], acc);
+                    if (r < 9)
+                        uv[(r / 3) * 5 + r % 3] = acc;
+                    else
+                        u25 = acc;
+                }
+                // even-odd: y 0..2, x 3..4
+    #pragma unroll
+                for (int r = 0; r < 6; ++r) {
+                    float acc = 0.0f;
+    #pragma unroll
+                    for (int c = 0; c < 6; ++c)
+                        acc = fmaf(mb[90 + r * 6 + c], sv[(c / 2) * 5 + 3 + c % 2], acc);
+                    uv[(r / 2) * 5 + 3 + r % 2] = acc;
+                }
+                // odd-even: y 3..4, x 0..2
+    #pragma unroll
+                for (int r = 0; r < 6; ++r) {
+                    float acc = 0.0f;
+    #pragma unroll
+                    for (int c = 0; c < 6; ++c)
+                        acc = fmaf(mb[126 + r * 6 + c], sv[(3 + c / 3) * 5 + c % 3], acc);
+                    uv[(3 + r / 3) * 5 + r % 3] = acc;
+                }
+                // odd-odd: y 3..4, x 3..4
+    #pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float acc = 0.0f;
+    #pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        acc = fmaf(mb[162 + r * 4 + c], sv[(3 + c / 2) * 5 + 3 + c % 2], acc);
+                    uv[(3 + r / 2) * 5 + 3 + r % 2] = acc;
+                }
+                // back to nodes: transpose of the mirror transform, y then x
+    #pragma unroll
+                for (int i = 0; i < 5; ++i) {
+                    t[0 * 5 + i] = uv[0 * 5 + i] + uv[3 * 5 + i];
+                    t[4 * 5 + i] = uv[0 * 5 + i] - uv[3 * 5 + i];
+                    t[1 * 5 + i] = uv[1 * 5 + i] + uv[4 * 5 + i];
+                    t[3 * 5 + i] = uv[1 * 5 + i] - uv[4 * 5 + i];
+                    t[2 * 5 + i] = uv[2 * 5 + i];
+                }
+    #pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    const float *y = &t[k * 5];
+                    w[k * 5 + 0] = y[0] + y[3];
+                    w[k * 5 + 4] = y[0] - y[3];
+                    w[k * 5 + 1] = y[1] + y[4];
+                    w[k * 5 + 3] = y[1] - y[4];
+                    w[k * 5 + 2] = y[2];
+                }
+                w[25] = u25;
+                cur = wy;
+            }
+            float v;
+            if (bad) {
+                // a non-finite neighbour: bilinear on the node's cell corners
+                const int i0 = s_i0[c], i1 = s_i1[c], j0 = s_j0[r], j1 = s_j1[r];
+                const float t = s_t[c], s = s_s[r];
+                const float q00 = at(j0, i0), q10 = at(j0, i1);
+                const float q01 = at(j1, i0), q11 = at(j1, i1);
+                const float top = q00 + t * (q10 - q00);
+                const float bot = q01 + t * (q11 - q01);
+                v = top + s * (bot - top);
+            } else {
+                const float dv = s_dv[r];
+                float acc = 0.0f;
+    #pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    const float e = ((float)k - dv) * p.fdy;
+                    const float ey2 = e * e * p.c2;
+    #pragma unroll
+                    for (int i = 0; i < 5; ++i) {
+                        const float t = __builtin_amdgcn_sqrtf(ex2[i] + ey2);
+                        if constexpr (kSeries) {
+                            // 1 - exp(-t) = t (1 - t/2 (1 - t/3 (... (1 - t/7))))
+                            float g = fmaf(-t, 1.0f / 7.0f, 1.0f);
+                            g = fmaf(-t * (1.0f / 6.0f), g, 1.0f);
+                            g = fmaf(-t * (1.0f / 5.0f), g, 1.0f);
+                            g = fmaf(-t * (1.0f / 4.0f), g, 1.0f);
+                            g = fmaf(-t * (1.0f / 3.0f), g, 1.0f);
+                            g = fmaf(-t * 0.5f, g, 1.0f);
+                            acc = fmaf(t * g, w[k * 5 + i], acc);
+                        } else {
+                            acc = fmaf(__builtin_amdgcn_exp2f(-t), w[k * 5 + i], acc);
+                        }
                     }
                 }
+                v = kSeries ? zc + (w[25] + acc) : zc + (w[25] - acc);
             }
-            v = kSeries ? zc + (w[25] + acc) : zc + (w[25] - acc);
+            p.dst[(int64_t)(row0 + r) * p.dnx + col0 + c] = v;
         }
-        p.dst[(int64_t)(row0 + r) * p.dnx + col0 + c] = v;
-    }
+    };
+    if (staged)
+        walk(std::true_type{});
+    else
+        walk(std::false_type{});
 }
 
 // Inverse of the 26 x 26 kriging matrix for node spacing (dx, dy) and range a,
