@@ -130,6 +130,18 @@ struct RowItem {
     SoA o;
 };
 
+// Pointers that reach a kernel inside a descriptor in memory cannot be told
+// from LDS pointers by the compiler, which then emits flat accesses; an
+// explicitly global-typed copy gives global loads and stores (32-bit offsets,
+// no LDS counter waits).
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gptr<T> gmem(T *p)
+{
+    return (gptr<T>)p;
+}
+
 // Batched launches: block b belongs to the item i with off[i] <= b < off[i+1]
 // (off ascending, count items; empty items have off[i] == off[i+1]).
 __device__ inline int item_of(const int32_t *off, int count, int b)

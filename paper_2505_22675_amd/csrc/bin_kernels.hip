@@ -324,18 +324,19 @@ constexpr int kRunsMax = 8;              // row runs per wave for the grouped re
 
 __device__ void row_hist_block(const RowItem &it, int blk, int *s_cnt)
 {
-    const double *__restrict__ x = it.x;
-    const double *__restrict__ y = it.y;
-    const double *__restrict__ z = it.z;
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const auto x = gmem(it.x);
+    const auto y = gmem(it.y);
+    const auto z = gmem(it.z);
     const int64_t n = it.n;
     const double x0 = it.x0, y0 = it.y0, lo = it.lo, hix = it.hix, hiy = it.hiy;
     const int32_t s = it.s, hB = it.hB, nby = it.nby;
-    int32_t *__restrict__ row_count = it.row_count;
-    int32_t *__restrict__ rowid = it.rowid;
-    int32_t *__restrict__ pos = it.pos;
-    int32_t *__restrict__ colkey = it.colkey;
-    int4 *__restrict__ rec = it.rec;
-    int32_t *__restrict__ drops = it.drops;
+    const auto row_count = gmem(it.row_count);
+    const auto rowid = gmem(it.rowid);
+    const auto pos = gmem(it.pos);
+    const auto colkey = gmem(it.colkey);
+    const auto rec = gmem(reinterpret_cast<v4i *>(it.rec));
+    const auto drops = gmem(it.drops);
     for (int r = threadIdx.x; r < nby; r += kThreads)
         s_cnt[r] = 0;
     __syncthreads();
@@ -360,7 +361,7 @@ __device__ void row_hist_block(const RowItem &it, int blk, int *s_cnt)
                     const int qx = (int)rint((tx - rx) * 32768.0);
                     const int qy = (int)rint((ty - ry) * 32768.0);
                     const uint32_t rr = ((uint32_t)qx & 0xffffu) | ((uint32_t)qy << 16);
-                    rec[i] = make_int4(X, Y, (int)rr, __float_as_int((float)zi));
+                    rec[i] = v4i{X, Y, (int)rr, __float_as_int((float)zi)};
                     colkey[i] = (X + hB) >> s;
                     row[j] = (Y + hB) >> s;
                 } else {
@@ -401,7 +402,8 @@ __device__ void row_hist_block(const RowItem &it, int blk, int *s_cnt)
     for (int r = threadIdx.x; r < nby; r += kThreads) {
         const int c = s_cnt[r];
         if (c)
-            s_cnt[r] = atomicAdd(&row_count[r], c);
+            s_cnt[r] = __hip_atomic_fetch_add(&row_count[r], c, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
 #pragma unroll
@@ -432,7 +434,7 @@ __device__ void row_hist_block(const RowItem &it, int blk, int *s_cnt)
 // their rows: key = bin column << 32 | original index.
 __device__ void row_scatter_block(const RowItem &it, int blk, int *s_rs, int *lds)
 {
-    const int32_t *__restrict__ cnt = it.row_count;
+    const auto cnt = gmem(it.row_count);
     const int32_t nby = it.nby;
     int carry = 0;
     for (int c = 0; c < nby; c += kThreads) {
@@ -446,10 +448,10 @@ __device__ void row_scatter_block(const RowItem &it, int blk, int *s_rs, int *ld
     }
     __syncthreads();
     if (blk == 0) {
-        int32_t *__restrict__ start = it.row_start;
+        const auto start = gmem(it.row_start);
         for (int i = threadIdx.x; i < nby; i += kThreads)
             start[i] = s_rs[i];
-        const int32_t *__restrict__ drops = it.drops;
+        const auto drops = gmem(it.drops);
         long long nbad = 0, nout = 0;
         for (int b = threadIdx.x; b < it.nblk; b += kThreads) {
             nbad += drops[2 * b];
@@ -469,15 +471,19 @@ __device__ void row_scatter_block(const RowItem &it, int blk, int *s_rs, int *ld
             it.stats[0] = (unsigned long long)carry;
         }
     }
+    const auto rowid = gmem(it.rowid);
+    const auto pos = gmem(it.pos);
+    const auto colkey = gmem(it.colkey);
+    const auto keys = gmem(it.keys);
     const int64_t base = (int64_t)blk * (kThreads * kScatterPer) + threadIdx.x;
 #pragma unroll
     for (int j = 0; j < kScatterPer; ++j) {
         const int64_t i = base + (int64_t)j * kThreads;
         if (i < it.n) {
-            const int r = it.rowid[i];
+            const int r = rowid[i];
             if (r >= 0)
-                it.keys[s_rs[r] + it.pos[i]] =
-                    ((unsigned long long)(uint32_t)it.colkey[i] << 32) | (uint32_t)i;
+                keys[s_rs[r] + pos[i]] =
+                    ((unsigned long long)(uint32_t)colkey[i] << 32) | (uint32_t)i;
         }
     }
 }
@@ -486,9 +492,10 @@ __device__ void row_scatter_block(const RowItem &it, int blk, int *s_rs, int *ld
 // padded with +inf up to a power of two, and pairs whose upper element lies in
 // the padding are skipped (the mirrored first step of each merge keeps every
 // comparison ascending, so padding never moves).  Whole block, any memory.
-template <class T>
-__device__ void block_bitonic_sort(T *a, int n)
+template <class P>
+__device__ void block_bitonic_sort(P a, int n)
 {
+    using T = unsigned long long;
     int npow = 1;
     while (npow < n)
         npow <<= 1;
@@ -551,9 +558,8 @@ static_assert(kThreads * kStageU <= kRowLds, "staged rows must take the LDS rank
 
 // for (k = threadIdx.x; k < n; k += kThreads) f(k, keys[r0 + k]), with kRowU
 // key loads issued before any is used
-template <class F>
-__device__ inline void for_row_keys(const unsigned long long *__restrict__ keys, int r0, int n,
-                                    F f)
+template <class KP, class F>
+__device__ inline void for_row_keys(KP keys, int r0, int n, F f)
 {
     for (int k0 = threadIdx.x; k0 < n; k0 += kThreads * kRowU) {
         unsigned long long kk[kRowU];
@@ -574,12 +580,27 @@ __device__ inline void for_row_keys(const unsigned long long *__restrict__ keys,
 __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
                                unsigned long long *s_k, int *lds)
 {
-    const unsigned long long *__restrict__ keys = it.keys;
-    const int32_t *__restrict__ row_start = it.row_start;
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const auto keys = gmem(it.keys);
+    const auto row_start = gmem(it.row_start);
     const int32_t nby = it.nby, nbx = it.nbx;
-    const int4 *__restrict__ rec = it.rec;
-    const SoA o = it.o;
-    int32_t *__restrict__ cell_start = it.cell_start;
+    const auto recv = gmem(reinterpret_cast<const v4i *>(it.rec));
+    const auto oX = gmem(it.o.X), oY = gmem(it.o.Y), oIdx = gmem(it.o.idx);
+    const auto oRes = gmem(it.o.res);
+    const auto oZ = gmem(it.o.z);
+    const auto cell_start = gmem(it.cell_start);
+    auto load_rec = [&](uint32_t i) {
+        const v4i q = recv[i];
+        return make_int4(q.x, q.y, q.z, q.w);
+    };
+    auto emit_g = [&](int pos, int orig) {
+        const int4 r = load_rec((uint32_t)orig);
+        oX[pos] = r.x;
+        oY[pos] = r.y;
+        oRes[pos] = (uint32_t)r.z;
+        oZ[pos] = __int_as_float(r.w);
+        oIdx[pos] = orig;
+    };
     const int r0 = row_start[row], n = row_start[row + 1] - r0;
     for (int bx = threadIdx.x; bx < nbx; bx += kThreads)
         s_h[bx] = 0;
@@ -588,7 +609,7 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
         atomicAdd(&s_h[(int)(key >> 32)], 1);
     });
     __syncthreads();
-    int32_t *cs = cell_start + (int64_t)row * nbx;
+    const auto cs = cell_start + (int64_t)row * nbx;
     int carry = 0, big = 0;
     for (int c = 0; c < nbx; c += kThreads) {
         const int bx = c + threadIdx.x;
@@ -605,16 +626,19 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
     if (row == nby - 1 && threadIdx.x == 0)
         cell_start[(int64_t)nby * nbx] = row_start[nby];
     if (__syncthreads_or(big)) {
-        unsigned long long *a = it.keys + r0;
         if (n <= kRowSortLds) {
             for (int k = threadIdx.x; k < n; k += kThreads)
                 s_k[k] = keys[r0 + k];
             __syncthreads();
-            a = s_k;
+            block_bitonic_sort(s_k, n);
+            for (int k = threadIdx.x; k < n; k += kThreads)
+                emit_g(r0 + k, (int)(uint32_t)(s_k[k] & 0xffffffffull));
+        } else {
+            const auto a = keys + r0;
+            block_bitonic_sort(a, n);
+            for (int k = threadIdx.x; k < n; k += kThreads)
+                emit_g(r0 + k, (int)(uint32_t)(a[k] & 0xffffffffull));
         }
-        block_bitonic_sort(a, n);
-        for (int k = threadIdx.x; k < n; k += kThreads)
-            emit(o, r0 + k, (int)(uint32_t)(a[k] & 0xffffffffull), rec);
         return;
     }
     if (n <= kRowLds) {
@@ -655,7 +679,7 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
 #pragma unroll
             for (int j = 0; j < kStageU; ++j)
                 if (pos[j] >= 0)
-                    rr[j] = rec[ix[j]];
+                    rr[j] = load_rec(ix[j]);
             int32_t *s_a = reinterpret_cast<int32_t *>(s_k);
             int32_t *s_b = s_a + kThreads * kStageU;
             __syncthreads();  // every rank is read: the index list is free
@@ -667,8 +691,8 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
                 }
             __syncthreads();
             for (int k = threadIdx.x; k < n; k += kThreads) {
-                o.X[r0 + k] = s_a[k];
-                o.Y[r0 + k] = s_b[k];
+                oX[r0 + k] = s_a[k];
+                oY[r0 + k] = s_b[k];
             }
             __syncthreads();
 #pragma unroll
@@ -679,8 +703,8 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
                 }
             __syncthreads();
             for (int k = threadIdx.x; k < n; k += kThreads) {
-                o.res[r0 + k] = (uint32_t)s_a[k];
-                o.z[r0 + k] = __int_as_float(s_b[k]);
+                oRes[r0 + k] = (uint32_t)s_a[k];
+                oZ[r0 + k] = __int_as_float(s_b[k]);
             }
             __syncthreads();
 #pragma unroll
@@ -689,7 +713,7 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
                     s_a[pos[j]] = (int)ix[j];
             __syncthreads();
             for (int k = threadIdx.x; k < n; k += kThreads)
-                o.idx[r0 + k] = s_a[k];
+                oIdx[r0 + k] = s_a[k];
             return;
         }
         // ranks first (LDS), then the kRowU record gathers in flight together
@@ -718,20 +742,20 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
 #pragma unroll
             for (int j = 0; j < kRowU; ++j)
                 if (pos[j] >= 0)
-                    rr[j] = rec[(uint32_t)kk[j]];
+                    rr[j] = load_rec((uint32_t)kk[j]);
 #pragma unroll
             for (int j = 0; j < kRowU; ++j)
                 if (pos[j] >= 0) {
-                    o.X[pos[j]] = rr[j].x;
-                    o.Y[pos[j]] = rr[j].y;
-                    o.res[pos[j]] = (uint32_t)rr[j].z;
-                    o.z[pos[j]] = __int_as_float(rr[j].w);
-                    o.idx[pos[j]] = (int)(uint32_t)kk[j];
+                    oX[pos[j]] = rr[j].x;
+                    oY[pos[j]] = rr[j].y;
+                    oRes[pos[j]] = (uint32_t)rr[j].z;
+                    oZ[pos[j]] = __int_as_float(rr[j].w);
+                    oIdx[pos[j]] = (int)(uint32_t)kk[j];
                 }
         }
         return;
     }
-    unsigned long long *__restrict__ tmp_keys = it.keys2;
+    const auto tmp_keys = gmem(it.keys2);
     for (int k = threadIdx.x; k < n; k += kThreads) {
         const unsigned long long key = keys[r0 + k];
         const int p = atomicAdd(&s_h[(int)(key >> 32)], 1);
@@ -747,7 +771,7 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
         int rank = 0;
         for (int q = b0; q < b1; ++q)
             rank += tmp_keys[r0 + q] < key ? 1 : 0;
-        emit(o, r0 + b0 + rank, (int)(uint32_t)(key & 0xffffffffull), rec);
+        emit_g(r0 + b0 + rank, (int)(uint32_t)(key & 0xffffffffull));
     }
 }
 
