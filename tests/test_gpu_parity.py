@@ -239,7 +239,10 @@ def test_cfg2_binning_counts(ag, orc, cfg2_run):
 
 @pytest.mark.parametrize("src_shape,dst_shape,nan_frac", [
     ((64, 64), (128, 128), 0.0), ((97, 45), (194, 90), 0.02),
-    ((50, 70), (33, 101), 0.05), ((1, 7), (3, 15), 0.0), ((33, 33), (33, 33), 0.1)])
+    ((50, 70), (33, 101), 0.05), ((1, 7), (3, 15), 0.0), ((33, 33), (33, 33), 0.1),
+    # strong downsampling: a patch's source rectangle exceeds the LDS stage
+    # and corners are read from global memory
+    ((120, 4000), (30, 1100), 0.02)])
 def test_bilinear_parity(ag, orc, src_shape, dst_shape, nan_frac):
     sh, sw = src_shape
     dh, dw = dst_shape
@@ -295,7 +298,8 @@ def test_bilinear_cfg2_upsample(ag, orc, cfg2_run):
 @pytest.mark.parametrize("src_shape,dst_shape,nan_frac", [
     ((64, 64), (128, 128), 0.0), ((97, 45), (194, 90), 0.02),
     ((50, 70), (33, 101), 0.05), ((1, 7), (3, 15), 0.0), ((2, 3), (5, 9), 0.0),
-    ((33, 33), (33, 33), 0.1), ((300, 1100), (600, 2200), 0.01)])
+    ((33, 33), (33, 33), 0.1), ((300, 1100), (600, 2200), 0.01),
+    ((120, 4000), (30, 1100), 0.02)])   # taps from global memory (no LDS stage)
 def test_bicubic_parity(ag, orc, src_shape, dst_shape, nan_frac):
     sh, sw = src_shape
     dh, dw = dst_shape
