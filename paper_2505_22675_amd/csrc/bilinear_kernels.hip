@@ -43,96 +43,163 @@ __device__ inline void patch_of(int ncb, int nrb, int *bx, int *by)
     *by = t / ncb;
 }
 
-// One block owns a 1024-column x 8-row patch of the destination.  The FP64
-// axis maps of its columns and rows are computed once into LDS; the source
-// rectangle the patch reads is staged into LDS with coalesced loads when it
-// fits (otherwise corners are gathered from global memory); every thread then
-// produces four consecutive nodes per row with one 16-byte streaming store.
+// One block owns a 1024-column band of kBilGroups row groups of 8 rows each.
+// The FP64 axis maps of its columns are computed once into LDS, those of its
+// rows likewise; each row group's source rectangle is staged into LDS when it
+// fits (otherwise corners are gathered from global memory), and the next
+// group's rectangle is loaded into registers while the current group is
+// blended and stored, so the reads' latency hides behind the stores.  Every
+// thread produces four consecutive nodes per row with one 16-byte streaming
+// store.
+constexpr int kBilGroups = 4;  // row groups per block
+constexpr int kBilPf = 12;     // prefetched values per thread (rectangles up to 3072 values)
+
 __global__ __launch_bounds__(kBilThreads) void k_bilinear(BilArgs p)
 {
     __shared__ int s_i0[kBilCols], s_i1[kBilCols];
     __shared__ float s_t[kBilCols];
-    __shared__ int s_j0[kBilRows], s_j1[kBilRows];
-    __shared__ float s_s[kBilRows];
+    __shared__ int s_j0[kBilGroups * kBilRows], s_j1[kBilGroups * kBilRows];
+    __shared__ float s_s[kBilGroups * kBilRows];
     __shared__ float s_src[kBilStage];
+    const int ngroups = (p.dny + kBilRows - 1) / kBilRows;
     int pbx, pby;
-    patch_of((p.dnx + kBilCols - 1) / kBilCols, (p.dny + kBilRows - 1) / kBilRows, &pbx, &pby);
+    patch_of((p.dnx + kBilCols - 1) / kBilCols, (ngroups + kBilGroups - 1) / kBilGroups, &pbx,
+             &pby);
     const int col0 = pbx * kBilCols;
-    const int row0 = pby * kBilRows;
+    const int g0 = pby * kBilGroups;               // first row group of the block
+    const int ng = min(kBilGroups, ngroups - g0);  // row groups of the block
     const int ncol = min(kBilCols, p.dnx - col0);
-    const int nrow = min(kBilRows, p.dny - row0);
     for (int c = threadIdx.x; c < kBilCols; c += kBilThreads) {
         const Axis a = axis_of(p.dx0, p.ddx, min(col0 + c, p.dnx - 1), p.sx0, p.sdx, p.snx);
         s_i0[c] = a.i0;
         s_i1[c] = a.i1;
         s_t[c] = a.t;
     }
-    if (threadIdx.x < kBilRows) {
-        const Axis a = axis_of(p.dy0, p.ddy, min(row0 + (int)threadIdx.x, p.dny - 1), p.sy0,
-                               p.sdy, p.sny);
+    if (threadIdx.x < kBilGroups * kBilRows) {
+        const int row = min(g0 * kBilRows + (int)threadIdx.x, p.dny - 1);
+        const Axis a = axis_of(p.dy0, p.ddy, row, p.sy0, p.sdy, p.sny);
         s_j0[threadIdx.x] = a.i0;
         s_j1[threadIdx.x] = a.i1;
         s_s[threadIdx.x] = a.t;
     }
     __syncthreads();
-    // source rectangle read by the patch (the maps are monotone)
+    // source columns read by the band (the maps are monotone)
     const int il = s_i0[0], ih = s_i1[ncol - 1];
-    const int jl = s_j0[0], jh = s_j1[nrow - 1];
-    const int sw = ih - il + 1, sh = jh - jl + 1;
-    const bool staged = (long long)sw * sh <= kBilStage;
-    if (staged) {
-        stage_rect(p.src, p.snx, jl, il, sw, sh, s_src, kBilThreads);
-        __syncthreads();
-    }
+    const int sw = ih - il + 1;
+    // source rows (first, count) of row group g
+    auto rows_of = [&](int g) {
+        const int nrow = min(kBilRows, p.dny - (g0 + g) * kBilRows);
+        const int jl = s_j0[g * kBilRows];
+        return make_int2(jl, s_j1[g * kBilRows + nrow - 1] - jl + 1);
+    };
+    // this thread's share of a rectangle: element e = threadIdx.x + k
+    // kBilThreads at (row e / sw, column e % sw), walked incrementally
+    float pf[kBilPf];
+    auto fetch = [&](int jl, int sh) {
+        const int n = sw * sh;
+        const int t = (int)threadIdx.x;
+        if (t >= n)
+            return;
+        int r = t / sw, cc = t - r * sw;
+        const int dr = kBilThreads / sw, dc = kBilThreads - dr * sw;
+        const float *row = p.src + (int64_t)(jl + r) * p.snx + il;
+#pragma unroll
+        for (int k = 0; k < kBilPf; ++k) {
+            if (t + k * kBilThreads < n)
+                pf[k] = row[cc];
+            cc += dc;
+            int step = dr;
+            if (cc >= sw) {
+                cc -= sw;
+                ++step;
+            }
+            row += (int64_t)step * p.snx;
+        }
+    };
+    auto place = [&](int sh) {
+        const int n = sw * sh;
+#pragma unroll
+        for (int k = 0; k < kBilPf; ++k) {
+            const int e = (int)threadIdx.x + k * kBilThreads;
+            if (e < n)
+                s_src[e] = pf[k];
+        }
+    };
     const int c = threadIdx.x * 4;
-    if (c >= ncol)
-        return;
     int i0[4], i1[4];
     float t[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        i0[k] = s_i0[c + k];
-        i1[k] = s_i1[c + k];
-        t[k] = s_t[c + k];
+        i0[k] = s_i0[min(c + k, kBilCols - 1)];
+        i1[k] = s_i1[min(c + k, kBilCols - 1)];
+        t[k] = s_t[min(c + k, kBilCols - 1)];
     }
     const bool vec = c + 4 <= ncol && (p.dnx & 3) == 0 &&
                      (reinterpret_cast<uintptr_t>(p.dst) & 15) == 0;
-    for (int r = 0; r < nrow; ++r) {
-        const float s = s_s[r];
-        float v[4];
-        if (staged) {
-            const float *r0 = s_src + (s_j0[r] - jl) * sw - il;
-            const float *r1 = s_src + (s_j1[r] - jl) * sw - il;
+    int2 rc = rows_of(0);
+    bool staged = (long long)sw * rc.y <= kBilStage;
+    if (staged)
+        stage_rect(p.src, p.snx, rc.x, il, sw, rc.y, s_src, kBilThreads);
+    __syncthreads();
+    for (int g = 0; g < ng; ++g) {
+        const int2 nx = g + 1 < ng ? rows_of(g + 1) : make_int2(0, 0);
+        const bool nstaged = g + 1 < ng && (long long)sw * nx.y <= kBilStage;
+        // small rectangles (2x upsampling: about 2600 values) are loaded into
+        // registers now and land in LDS after this group's stores
+        const bool pref = nstaged && sw * nx.y <= kBilThreads * kBilPf;
+        if (pref)
+            fetch(nx.x, nx.y);
+        const int row0 = (g0 + g) * kBilRows;
+        const int nrow = min(kBilRows, p.dny - row0);
+        const int jl = rc.x;
+        if (c < ncol) {
+            for (int r = 0; r < nrow; ++r) {
+                const int q = g * kBilRows + r;
+                const float s = s_s[q];
+                float v[4];
+                if (staged) {
+                    const float *r0 = s_src + (s_j0[q] - jl) * sw - il;
+                    const float *r1 = s_src + (s_j1[q] - jl) * sw - il;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float q00 = r0[i0[k]], q10 = r0[i1[k]];
-                const float q01 = r1[i0[k]], q11 = r1[i1[k]];
-                const float top = q00 + t[k] * (q10 - q00);
-                const float bot = q01 + t[k] * (q11 - q01);
-                v[k] = top + s * (bot - top);
-            }
-        } else {
-            const float *r0 = p.src + (int64_t)s_j0[r] * p.snx;
-            const float *r1 = p.src + (int64_t)s_j1[r] * p.snx;
+                    for (int k = 0; k < 4; ++k) {
+                        const float q00 = r0[i0[k]], q10 = r0[i1[k]];
+                        const float q01 = r1[i0[k]], q11 = r1[i1[k]];
+                        const float top = q00 + t[k] * (q10 - q00);
+                        const float bot = q01 + t[k] * (q11 - q01);
+                        v[k] = top + s * (bot - top);
+                    }
+                } else {
+                    const float *r0 = p.src + (int64_t)s_j0[q] * p.snx;
+                    const float *r1 = p.src + (int64_t)s_j1[q] * p.snx;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float q00 = r0[i0[k]], q10 = r0[i1[k]];
-                const float q01 = r1[i0[k]], q11 = r1[i1[k]];
-                const float top = q00 + t[k] * (q10 - q00);
-                const float bot = q01 + t[k] * (q11 - q01);
-                v[k] = top + s * (bot - top);
+                    for (int k = 0; k < 4; ++k) {
+                        const float q00 = r0[i0[k]], q10 = r0[i1[k]];
+                        const float q01 = r1[i0[k]], q11 = r1[i1[k]];
+                        const float top = q00 + t[k] * (q10 - q00);
+                        const float bot = q01 + t[k] * (q11 - q01);
+                        v[k] = top + s * (bot - top);
+                    }
+                }
+                float *out = p.dst + (int64_t)(row0 + r) * p.dnx + col0 + c;
+                if (vec) {
+                    // streaming store: the destination is not re-read by this kernel
+                    typedef float f4v __attribute__((ext_vector_type(4)));
+                    const f4v vv = {v[0], v[1], v[2], v[3]};
+                    __builtin_nontemporal_store(vv, reinterpret_cast<f4v *>(out));
+                } else {
+                    for (int k = 0; k < 4 && c + k < ncol; ++k)
+                        out[k] = v[k];
+                }
             }
         }
-        float *out = p.dst + (int64_t)(row0 + r) * p.dnx + col0 + c;
-        if (vec) {
-            // streaming store: the destination is not re-read by this kernel
-            typedef float f4v __attribute__((ext_vector_type(4)));
-            const f4v vv = {v[0], v[1], v[2], v[3]};
-            __builtin_nontemporal_store(vv, reinterpret_cast<f4v *>(out));
-        } else {
-            for (int k = 0; k < 4 && c + k < ncol; ++k)
-                out[k] = v[k];
-        }
+        __syncthreads();  // every read of this group's rectangle is done
+        if (pref)
+            place(nx.y);
+        else if (nstaged)
+            stage_rect(p.src, p.snx, nx.x, il, sw, nx.y, s_src, kBilThreads);
+        __syncthreads();
+        rc = nx;
+        staged = nstaged;
     }
 }
 
@@ -336,8 +403,9 @@ auv_status launch_bilinear(const float *src, const auv_grid_desc &s, float *dst,
     p.sny = s.ny;
     p.dnx = d.nx;
     p.dny = d.ny;
+    const int ngroups = (d.ny + kBilRows - 1) / kBilRows;
     const unsigned grid = (unsigned)(((d.nx + kBilCols - 1) / kBilCols) *
-                                     ((d.ny + kBilRows - 1) / kBilRows));
+                                     ((ngroups + kBilGroups - 1) / kBilGroups));
     k_bilinear<<<grid, kBilThreads, 0, st>>>(p);
     AUV_HIP(hipGetLastError());
     return AUV_OK;
