@@ -503,6 +503,13 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
 
     // this lane's window cell in each chunk
     int ci[kChunks], cj[kChunks], iD[kChunks], jD[kChunks], qo[kChunks];
+    // exact form: (row, column) of the cell as two 16-bit halves; the cell of
+    // a record's window lies in the tile when both halves of cell + window
+    // origin are in [0, 16) -- one packed add and one mask test.  Edge tiles
+    // are treated as whole 16 x 16 tiles: nodes past the grid edge collect
+    // sums that are never read (finalisation covers in-grid nodes only).
+    static_assert(kTW == 16 && kTH == 16, "the packed tile test assumes 16 x 16 tiles");
+    uint32_t pc[kChunks];
 #pragma unroll
     for (int t = 0; t < kChunks; ++t) {
         const int c = t * 64 + lane;
@@ -513,6 +520,7 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
         iD[t] = sext23(v ? ci[t] * g.DYl : 0);
         jD[t] = sext23(v ? cj[t] * g.DXl : 0);
         qo[t] = v ? ci[t] * kRS + cj[t] : 0;
+        pc[t] = v ? ((uint32_t)ci[t] << 16) | (uint32_t)cj[t] : 0x40004000u;
     }
 
     __syncthreads();  // the previous tile of this wave is finished with LDS
@@ -619,7 +627,11 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                 const int slot = __builtin_amdgcn_mbcnt_hi(
                     (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
                 const int qb = pia * kRS + pjb;
-                sm.r0[2 * slot] = make_int4(pia, pjb, qb * 8, qb * 4);
+                // exact form: window origin as packed 16-bit (row, column)
+                const int o0 = kExact ? (int)((((uint32_t)pia & 0xffffu) << 16) |
+                                              ((uint32_t)pjb & 0xffffu))
+                                      : pia;
+                sm.r0[2 * slot] = make_int4(o0, pjb, qb * 8, qb * 4);
                 sm.r1[2 * slot] = make_int4(__float_as_int(prx), __float_as_int(pry),
                                         __float_as_int(pdz), pidx);
                 if constexpr (!kExact)
@@ -660,8 +672,16 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                 const int qb = qb4 >> 2;
 #pragma unroll
                 for (int t = 0; t < kChunks; ++t) {
-                    const bool in = (unsigned)(ia + ci[t]) < (unsigned)th &&
-                                    (unsigned)(jb + cj[t]) < (unsigned)tw;
+                    bool in;
+                    if constexpr (kExact) {
+                        typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+                        const us2 sum = __builtin_bit_cast(us2, pc[t]) +
+                                        __builtin_bit_cast(us2, (uint32_t)ia);
+                        in = (__builtin_bit_cast(uint32_t, sum) & 0xfff0fff0u) == 0u;
+                    } else {
+                        in = (unsigned)(ia + ci[t]) < (unsigned)th &&
+                             (unsigned)(jb + cj[t]) < (unsigned)tw;
+                    }
                     const int dX = sx - jD[t], dY = sy - iD[t];
                     // ranking key and member test: exact lattice D^2, or the
                     // variant's FP32 squared distance (bit pattern)
