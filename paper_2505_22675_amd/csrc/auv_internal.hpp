@@ -124,6 +124,9 @@ struct RowItem {
     double x0, y0, lo, hix, hiy;
     int32_t s, hB, nbx, nby;
     int32_t nblk;  // k_row_hist blocks of this item (drop partials)
+    // optional (serving): lattice box X min, Y min, X max, Y max of the
+    // binned soundings, widened atomically from a caller-seeded empty box
+    int32_t *bbox;
     int32_t *row_count, *row_start, *rowid, *pos, *colkey, *drops, *cell_start;
     int4 *rec;
     unsigned long long *keys, *keys2, *stats;

@@ -343,6 +343,7 @@ __device__ void row_hist_block(const RowItem &it, int blk, int *s_cnt)
     const int64_t base = (int64_t)blk * kRowChunk + threadIdx.x;
     int row[kRowPerThread], lr[kRowPerThread];
     int bad = 0, out = 0;
+    int blx = INT_MAX, bly = INT_MAX, bhx = INT_MIN, bhy = INT_MIN;  // box of the binned
 #pragma unroll
     for (int j = 0; j < kRowPerThread; ++j) {
         const int64_t i = base + (int64_t)j * kThreads;
@@ -364,6 +365,10 @@ __device__ void row_hist_block(const RowItem &it, int blk, int *s_cnt)
                     rec[i] = v4i{X, Y, (int)rr, __float_as_int((float)zi)};
                     colkey[i] = (X + hB) >> s;
                     row[j] = (Y + hB) >> s;
+                    blx = min(blx, X);
+                    bhx = max(bhx, X);
+                    bly = min(bly, Y);
+                    bhy = max(bhy, Y);
                 } else {
                     out += 1;
                 }
@@ -412,6 +417,21 @@ __device__ void row_hist_block(const RowItem &it, int blk, int *s_cnt)
         if (i < n) {
             rowid[i] = row[j];
             pos[i] = row[j] >= 0 ? s_cnt[row[j]] + lr[j] : 0;
+        }
+    }
+    if (it.bbox) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            blx = min(blx, __shfl_xor(blx, d, 64));
+            bly = min(bly, __shfl_xor(bly, d, 64));
+            bhx = max(bhx, __shfl_xor(bhx, d, 64));
+            bhy = max(bhy, __shfl_xor(bhy, d, 64));
+        }
+        if (lane_id() == 0 && blx <= bhx) {
+            atomicMin(&it.bbox[0], blx);
+            atomicMin(&it.bbox[1], bly);
+            atomicMax(&it.bbox[2], bhx);
+            atomicMax(&it.bbox[3], bhy);
         }
     }
     // per-block drop counters (summed by block 0 of k_row_scatter: a device-wide atomic on
@@ -962,6 +982,7 @@ RowItem make_row_item(const auv_grid *g, const BinGeom &geom, const double *x,
     it.nbx = geom.nbx;
     it.nby = geom.nby;
     it.nblk = n > 0 ? (int32_t)grid_for(n, kRowChunk) : 0;
+    it.bbox = nullptr;
     it.row_count = w.row_count;
     it.row_start = w.row_start;
     it.rowid = w.rowid;

@@ -4,12 +4,13 @@
 // vehicles in batched mode) enqueues on the session stream:
 //   H2D copies of the launch table and of each request's slot (bounding-box
 //   seed + x, y, z)
-//   k_serve_bbox        conservative lattice bounding box of each request
-//   batched row binning (the kernels behind auv_bin_points)
+//   batched row binning (the kernels behind auv_bin_points); its histogram
+//                       kernel also widens each request's lattice bounding
+//                       box over the binned soundings
 //   k_serve_update<c>   persistent: (request, node tile) work over the tiles
 //                       within the radius of each request's bounding box;
 //                       the window-form gather accumulates the tile in LDS
-//                       (four waves per tile, combined in fixed order), then
+//                       (16 waves per tile, combined in fixed order), then
 //                       each node's resident sums get one read-modify-write
 //   an event, which the worker thread observes to complete the tickets.
 // A vehicle has at most one request per launch and launches run in stream
@@ -36,8 +37,6 @@ namespace auv {
 namespace {
 
 constexpr int kMaxBatchReq = 64;
-constexpr int kBboxThreads = 256;
-constexpr int kBboxPer = 2048;  // soundings per k_serve_bbox block
 constexpr size_t kSlotHeader = 256;
 
 struct ServeItem {
@@ -45,69 +44,8 @@ struct ServeItem {
     IdwArgs a;
     WinGeom g;
     int32_t ntx;
-    const int32_t *bbox;  // X min, Y min, X max, Y max (lattice units, conservative)
+    const int32_t *bbox;  // X min, Y min, X max, Y max (lattice units, binned soundings)
 };
-
-struct BboxItem {
-    const double *x, *y;
-    int64_t n;
-    double x0, y0;
-    int32_t *bbox;
-};
-
-// Conservative bounding box of the finite soundings: floor / ceil of the
-// lattice coordinate brackets the rounded coordinate the binning uses.
-__global__ __launch_bounds__(kBboxThreads) void k_serve_bbox(const BboxItem *__restrict__ items,
-                                                             const int32_t *__restrict__ off,
-                                                             int count)
-{
-    const int i = item_of(off, count, blockIdx.x);
-    const BboxItem &it = items[i];
-    const int64_t base = (int64_t)(blockIdx.x - off[i]) * kBboxPer;
-    int lx = INT_MAX, ly = INT_MAX, hx = INT_MIN, hy = INT_MIN;
-    for (int j = threadIdx.x; j < kBboxPer; j += kBboxThreads) {
-        const int64_t k = base + j;
-        if (k < it.n) {
-            const double xi = it.x[k], yi = it.y[k];
-            if (isfinite(xi) && isfinite(yi)) {
-                const double tx = fmin(fmax((xi - it.x0) * kLatticePerMetre, -1073741824.0),
-                                       1073741824.0);
-                const double ty = fmin(fmax((yi - it.y0) * kLatticePerMetre, -1073741824.0),
-                                       1073741824.0);
-                lx = min(lx, (int)floor(tx));
-                hx = max(hx, (int)ceil(tx));
-                ly = min(ly, (int)floor(ty));
-                hy = max(hy, (int)ceil(ty));
-            }
-        }
-    }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        lx = min(lx, __shfl_xor(lx, d, 64));
-        ly = min(ly, __shfl_xor(ly, d, 64));
-        hx = max(hx, __shfl_xor(hx, d, 64));
-        hy = max(hy, __shfl_xor(hy, d, 64));
-    }
-    __shared__ int4 s_r[kBboxThreads / 64];
-    if ((threadIdx.x & 63) == 0)
-        s_r[threadIdx.x >> 6] = make_int4(lx, ly, hx, hy);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int4 r = s_r[0];
-        for (int w = 1; w < kBboxThreads / 64; ++w) {
-            r.x = min(r.x, s_r[w].x);
-            r.y = min(r.y, s_r[w].y);
-            r.z = max(r.z, s_r[w].z);
-            r.w = max(r.w, s_r[w].w);
-        }
-        if (r.x <= r.z) {
-            atomicMin(&it.bbox[0], r.x);
-            atomicMin(&it.bbox[1], r.y);
-            atomicMax(&it.bbox[2], r.z);
-            atomicMax(&it.bbox[3], r.w);
-        }
-    }
-}
 
 __device__ inline long long floor_div(long long a, long long b)
 {
@@ -323,7 +261,7 @@ struct Launch {
 
 // Launch table: device copy of what the kernels of one launch read.
 struct TableLayout {
-    size_t items, bbox, rows, offs, counters, bytes;
+    size_t items, rows, offs, counters, bytes;
 };
 
 TableLayout table_layout()
@@ -332,12 +270,10 @@ TableLayout table_layout()
     size_t o = 0;
     t.items = o;
     o += align256(sizeof(ServeItem) * kMaxBatchReq);
-    t.bbox = o;
-    o += align256(sizeof(BboxItem) * kMaxBatchReq);
     t.rows = o;
     o += align256(sizeof(RowItem) * kMaxBatchReq);
     t.offs = o;
-    o += align256(sizeof(int32_t) * 4 * (kMaxBatchReq + 1));
+    o += align256(sizeof(int32_t) * 3 * (kMaxBatchReq + 1));
     t.counters = o;
     o += align256(sizeof(int32_t) * 4);
     t.bytes = o;
@@ -488,14 +424,12 @@ auv_status enqueue_launch(auv_session *s, const std::vector<Pick> &picks, int ta
     char *th = s->table_host[table];
     char *td = s->table_dev[table];
     ServeItem *items = reinterpret_cast<ServeItem *>(th + L.items);
-    BboxItem *bb = reinterpret_cast<BboxItem *>(th + L.bbox);
     RowItem *rows = reinterpret_cast<RowItem *>(th + L.rows);
     int32_t *offs = reinterpret_cast<int32_t *>(th + L.offs);
     const int B = (int)picks.size();
-    int32_t *bbox_off = offs, *hist_off = offs + (B + 1), *scat_off = offs + 2 * (B + 1),
-            *sort_off = offs + 3 * (B + 1);
+    int32_t *hist_off = offs, *scat_off = offs + (B + 1), *sort_off = offs + 2 * (B + 1);
     int32_t *counters = reinterpret_cast<int32_t *>(th + L.counters);
-    bbox_off[0] = hist_off[0] = scat_off[0] = sort_off[0] = 0;
+    hist_off[0] = scat_off[0] = sort_off[0] = 0;
     bool chunks[win::kMaxChunks + 1] = {false, false, false, false, false};
     int64_t ntot = 0;
     int32_t max_nbx = 0, max_nby = 0;
@@ -508,7 +442,7 @@ auv_status enqueue_launch(auv_session *s, const std::vector<Pick> &picks, int ta
         BinWorkspace w;
         bin_workspace_layout(p.n, V.geom, s->slot_ws[p.slot], &w);
         rows[i] = make_row_item(&V.grid, V.geom, x, y, z, p.n, w);
-        bb[i] = BboxItem{x, y, p.n, V.grid.d.x0, V.grid.d.y0, reinterpret_cast<int32_t *>(dev)};
+        rows[i].bbox = reinterpret_cast<int32_t *>(dev);  // seeded empty by the submit
         ServeItem &it = items[i];
         std::memset(&it, 0, sizeof(it));
         auv_bin_view &v = it.bv;
@@ -535,7 +469,6 @@ auv_status enqueue_launch(auv_session *s, const std::vector<Pick> &picks, int ta
         it.ntx = (V.grid.d.nx + win::kTW - 1) / win::kTW;
         it.bbox = reinterpret_cast<const int32_t *>(dev);
         chunks[V.wg.nchunks] = true;
-        bbox_off[i + 1] = bbox_off[i] + (int32_t)((p.n + kBboxPer - 1) / kBboxPer);
         hist_off[i + 1] = hist_off[i] + row_hist_blocks(p.n);
         scat_off[i + 1] = scat_off[i] + row_scatter_blocks(p.n);
         sort_off[i + 1] = sort_off[i] + V.geom.nby;
@@ -547,7 +480,6 @@ auv_status enqueue_launch(auv_session *s, const std::vector<Pick> &picks, int ta
         counters[c] = 0;
     // device pointers inside the table
     ServeItem *d_items = reinterpret_cast<ServeItem *>(td + L.items);
-    BboxItem *d_bb = reinterpret_cast<BboxItem *>(td + L.bbox);
     RowItem *d_rows = reinterpret_cast<RowItem *>(td + L.rows);
     int32_t *d_offs = reinterpret_cast<int32_t *>(td + L.offs);
     int32_t *d_counters = reinterpret_cast<int32_t *>(td + L.counters);
@@ -556,11 +488,9 @@ auv_status enqueue_launch(auv_session *s, const std::vector<Pick> &picks, int ta
     for (const Pick &p : picks)
         AUV_HIP(hipMemcpyAsync(s->slot_dev[p.slot], s->slot_host[p.slot],
                                kSlotHeader + 24 * (size_t)p.n, hipMemcpyHostToDevice, st));
-    if (bbox_off[B] > 0)
-        k_serve_bbox<<<bbox_off[B], kBboxThreads, 0, st>>>(d_bb, d_offs, B);
-    AUV_TRY_S(launch_binning_batch(d_rows, d_offs + (B + 1), d_offs + 2 * (B + 1),
-                                   d_offs + 3 * (B + 1), B, hist_off[B], scat_off[B],
-                                   sort_off[B], max_nbx, max_nby, st));
+    AUV_TRY_S(launch_binning_batch(d_rows, d_offs, d_offs + (B + 1), d_offs + 2 * (B + 1), B,
+                                   hist_off[B], scat_off[B], sort_off[B], max_nbx, max_nby,
+                                   st));
     // as many persistent blocks as fit at once (8 waves per CU)
     const int per_cu = std::max(1, 8 / kServeParts);
     const int blocks = (int)std::min<int64_t>((int64_t)per_cu * s->cus, 16 + ntot / 256);
