@@ -22,6 +22,7 @@ struct BilArgs {
     double sx0, sy0, sdx, sdy;
     double dx0, dy0, ddx, ddy;
     int snx, sny, dnx, dny;
+    int groups;  // k_bilinear: row groups per block (1 .. kBilGroups)
 };
 
 constexpr int kBilThreads = 256;
@@ -43,8 +44,10 @@ __device__ inline void patch_of(int ncb, int nrb, int *bx, int *by)
     *by = t / ncb;
 }
 
-// One block owns a 1024-column band of kBilGroups row groups of 8 rows each
-// (8 groups measured best: 2, 4, 8, 16 gave 73, 70, 68, 104 us at cfg2 2x).
+// One block owns a 1024-column band of p.groups row groups of 8 rows each:
+// up to kBilGroups while the launch keeps at least 1024 blocks (at cfg2 2x, 2,
+// 4, 8 and 16 groups gave 73, 70, 68 and 104 us), one when the rectangles
+// are too large to stage (then there is nothing to prefetch).
 // The FP64 axis maps of its columns are computed once into LDS, those of its
 // rows likewise; each row group's source rectangle is staged into LDS when it
 // fits (otherwise corners are gathered from global memory), and the next
@@ -52,7 +55,7 @@ __device__ inline void patch_of(int ncb, int nrb, int *bx, int *by)
 // blended and stored, so the reads' latency hides behind the stores.  Every
 // thread produces four consecutive nodes per row with one 16-byte streaming
 // store.
-constexpr int kBilGroups = 8;  // row groups per block
+constexpr int kBilGroups = 8;  // row groups per block, at most
 constexpr int kBilPf = 12;     // prefetched values per thread (rectangles up to 3072 values)
 
 __global__ __launch_bounds__(kBilThreads) void k_bilinear(BilArgs p)
@@ -64,11 +67,11 @@ __global__ __launch_bounds__(kBilThreads) void k_bilinear(BilArgs p)
     __shared__ float s_src[kBilStage];
     const int ngroups = (p.dny + kBilRows - 1) / kBilRows;
     int pbx, pby;
-    patch_of((p.dnx + kBilCols - 1) / kBilCols, (ngroups + kBilGroups - 1) / kBilGroups, &pbx,
+    patch_of((p.dnx + kBilCols - 1) / kBilCols, (ngroups + p.groups - 1) / p.groups, &pbx,
              &pby);
     const int col0 = pbx * kBilCols;
-    const int g0 = pby * kBilGroups;               // first row group of the block
-    const int ng = min(kBilGroups, ngroups - g0);  // row groups of the block
+    const int g0 = pby * p.groups;               // first row group of the block
+    const int ng = min(p.groups, ngroups - g0);  // row groups of the block
     const int ncol = min(kBilCols, p.dnx - col0);
     for (int c = threadIdx.x; c < kBilCols; c += kBilThreads) {
         const Axis a = axis_of(p.dx0, p.ddx, min(col0 + c, p.dnx - 1), p.sx0, p.sdx, p.snx);
@@ -76,7 +79,7 @@ __global__ __launch_bounds__(kBilThreads) void k_bilinear(BilArgs p)
         s_i1[c] = a.i1;
         s_t[c] = a.t;
     }
-    if (threadIdx.x < kBilGroups * kBilRows) {
+    if (threadIdx.x < p.groups * kBilRows) {
         const int row = min(g0 * kBilRows + (int)threadIdx.x, p.dny - 1);
         const Axis a = axis_of(p.dy0, p.ddy, row, p.sy0, p.sdy, p.sny);
         s_j0[threadIdx.x] = a.i0;
@@ -379,6 +382,7 @@ auv_status launch_bicubic(const float *src, const auv_grid_desc &s, float *dst,
     p.sny = s.ny;
     p.dnx = d.nx;
     p.dny = d.ny;
+    p.groups = 1;
     const unsigned grid = (unsigned)(((d.nx + kBilCols - 1) / kBilCols) *
                                      ((d.ny + kBilRows - 1) / kBilRows));
     k_bicubic<<<grid, kBilThreads, 0, st>>>(p);
@@ -405,8 +409,15 @@ auv_status launch_bilinear(const float *src, const auv_grid_desc &s, float *dst,
     p.dnx = d.nx;
     p.dny = d.ny;
     const int ngroups = (d.ny + kBilRows - 1) / kBilRows;
-    const unsigned grid = (unsigned)(((d.nx + kBilCols - 1) / kBilCols) *
-                                     ((ngroups + kBilGroups - 1) / kBilGroups));
+    const int64_t ncb = (d.nx + kBilCols - 1) / kBilCols;
+    // a row group's source rectangle, roughly: several groups per block only
+    // pay when it is staged (the next one is prefetched meanwhile)
+    const double rect = (kBilCols * d.dx / s.dx + 2.0) * (kBilRows * d.dy / s.dy + 2.0);
+    p.groups = rect > kBilStage
+                   ? 1
+                   : (int)std::max<int64_t>(1, std::min<int64_t>(kBilGroups,
+                                                                 ncb * ngroups / 1024));
+    const unsigned grid = (unsigned)(ncb * ((ngroups + p.groups - 1) / p.groups));
     k_bilinear<<<grid, kBilThreads, 0, st>>>(p);
     AUV_HIP(hipGetLastError());
     return AUV_OK;
