@@ -15,6 +15,7 @@ import argparse
 import gc
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -144,13 +145,26 @@ def _median_ms(fn, stream, reps):
     return float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
 
 
+def _cpu_median_ms(fn):
+    """Median wall time of fn() in ms over up to five runs (fewer once a second
+    has been spent; at least one), after one untimed run that starts the host
+    thread pool."""
+    fn()
+    times = []
+    while len(times) < 5 and (not times or sum(times) < 1.0):
+        c0 = time.perf_counter()
+        fn()
+        times.append(time.perf_counter() - c0)
+    return round(statistics.median(times) * 1e3, 3)
+
+
 GRID_A_POINTS = [10 ** 3, 10 ** 4, 10 ** 5, 10 ** 6, 10 ** 7, 10 ** 8]
 GRID_A_CPU_MAX = 10 ** 6
 RESAMPLERS = ("bilinear", "bicubic", "kriging")
 
 
 def cpu_grid_a(s, v, d, range_m):
-    """Oracle leg of the grid-A sweep: each resampler once, in ms."""
+    """Oracle leg of the grid-A sweep: median ms of each resampler."""
     import oracle
     oracle.build(force=False)
     th = host_threads()
@@ -159,12 +173,11 @@ def cpu_grid_a(s, v, d, range_m):
     src = v.astype("float64")
     out = {}
     for m in RESAMPLERS:
-        c0 = time.perf_counter()
         if m == "kriging":
-            oracle.kriging(og, src, od, range_m, nthreads=th)
+            fn = lambda: oracle.kriging(og, src, od, range_m, nthreads=th)
         else:
-            getattr(oracle, m)(og, src, od, nthreads=th)
-        out[f"cpu_{m}_ms"] = round((time.perf_counter() - c0) * 1e3, 3)
+            fn = lambda: getattr(oracle, m)(og, src, od, nthreads=th)
+        out[f"cpu_{m}_ms"] = _cpu_median_ms(fn)
     return out
 
 
@@ -268,7 +281,7 @@ def grid_b_report(ag, dev, with_cpu, n_fine=2048):
 
 
 def cpu_grid_b(c, range_m, radius):
-    """Oracle leg of the grid-B protocol: each fill once, in ms."""
+    """Oracle leg of the grid-B protocol: median ms of each fill."""
     import oracle
     oracle.build(force=False)
     th = host_threads()
@@ -278,14 +291,14 @@ def cpu_grid_b(c, range_m, radius):
     src = c["coarse"].astype("float64")
     out = {}
     for m in RESAMPLERS + ("idw",):
-        c0 = time.perf_counter()
         if m == "kriging":
-            oracle.kriging(oc, src, ot, range_m, nthreads=th)
+            fn = lambda: oracle.kriging(oc, src, ot, range_m, nthreads=th)
         elif m == "idw":
-            oracle.idw(ot, c["x"], c["y"], c["z"], radius, 2.0, 1, 0, bin_log2=19, nthreads=th)
+            fn = lambda: oracle.idw(ot, c["x"], c["y"], c["z"], radius, 2.0, 1, 0,
+                                    bin_log2=19, nthreads=th)
         else:
-            getattr(oracle, m)(oc, src, ot, nthreads=th)
-        out[m] = round((time.perf_counter() - c0) * 1e3, 3)
+            fn = lambda: getattr(oracle, m)(oc, src, ot, nthreads=th)
+        out[m] = _cpu_median_ms(fn)
     return out
 
 
