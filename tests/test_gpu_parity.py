@@ -242,7 +242,10 @@ def test_cfg2_binning_counts(ag, orc, cfg2_run):
     ((50, 70), (33, 101), 0.05), ((1, 7), (3, 15), 0.0), ((33, 33), (33, 33), 0.1),
     # strong downsampling: a patch's source rectangle exceeds the LDS stage
     # and corners are read from global memory
-    ((120, 4000), (30, 1100), 0.02)])
+    ((120, 4000), (30, 1100), 0.02),
+    # large enough for several row groups per block (four here): 875 row
+    # groups of 8 do not divide into fours and the last group has 7 rows
+    ((3500, 2500), (6999, 5000), 0.01)])
 def test_bilinear_parity(ag, orc, src_shape, dst_shape, nan_frac):
     sh, sw = src_shape
     dh, dw = dst_shape
