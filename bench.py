@@ -125,7 +125,31 @@ def cpu_baseline(s, up_desc, nodes):
                      f"FP64 IDW+nearest on all {nodes} nodes ({t_idw / reps:.3f} s each) + "
                      f"bilinear to 8192^2 ({t_bil / reps:.3f} s each)"}
     log(f"cpu baseline {out['value']:.3e} nodes/s over {reps} repetitions")
+    # brute force (every sounding tested at every node) on seeded sampled nodes
+    import numpy as np
+    sample = np.random.default_rng(2).choice(nodes, 16384, replace=False).astype(np.int64)
+    c0 = time.perf_counter()
+    oracle.idw(og, s.x, s.y, s.z, s.radius, s.power, s.min_pts, s.max_pts, bin_log2=-1,
+               nodes=sample, nthreads=th)
+    t_bf = time.perf_counter() - c0
+    out["brute_force_sample"] = {"nodes": int(sample.size), "seconds": round(t_bf, 3),
+                                 "pair_tests": int(sample.size) * int(s.n),
+                                 "nodes_per_s": round(sample.size / t_bf, 1)}
+    out["host"] = {"cpus": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+                   "model": cpu_model()}
+    log(f"cpu brute force: {sample.size} nodes in {t_bf:.2f} s")
     return out
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _median_ms(fn, stream, reps):
@@ -585,8 +609,10 @@ def main():
     stage = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(3)]
                       for k in range(K)])
     st_ms = stage.mean(axis=0)
+    step_ev = np.array([evs[k][0].elapsed_time(evs[k][3]) for k in range(K)])
     log(f"timed {K} steps: {ms_per_step:.4f} ms/step; stages bin/idw/bilinear = "
         f"{st_ms[0]:.4f}/{st_ms[1]:.4f}/{st_ms[2]:.4f} ms")
+    nan_frac = float(torch.isnan(z_out).float().mean().item())
 
     nodes = s.grid.nx * s.grid.ny
     _, _, counts = ag.auv_bins_export(bins)
@@ -613,6 +639,36 @@ def main():
         "instructions": valu, "achieved_per_s": round(valu / (dur[dom] * 1e-3), 1),
         "peak_per_s": VALU_ISSUE_PEAK,
         "frac": round(valu / (dur[dom] * 1e-3) / VALU_ISSUE_PEAK, 4)}
+
+    # the practical ceiling in this run: a 256 MiB device-to-device copy
+    ca = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    cb = torch.empty_like(ca)
+    copy_ms = _median_ms(lambda: cb.copy_(ca), stream, 20)
+    roofline["copy_GBs"] = round(2 * ca.numel() * 4 / (copy_ms * 1e-3) / 1e9, 1)
+    del ca, cb
+    log(f"device copy: {roofline['copy_GBs']:.0f} GB/s")
+
+    # cold steps: 512 MiB read before each one, so that no input or
+    # intermediate of the previous step is left in the 256 MB last-level cache
+    # (a read, not a write: dirty lines of a write flush would drain during
+    # the step and slow its own writes)
+    flush = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+    cold_ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(20)]
+    for k in range(20):
+        flush.sum()
+        step(cold_ev[k])
+    torch.cuda.synchronize()
+    del flush
+    cold_stage = np.array([[cold_ev[k][j].elapsed_time(cold_ev[k][j + 1]) for j in range(3)]
+                           for k in range(20)])
+    cold_step = np.array([cold_ev[k][0].elapsed_time(cold_ev[k][3]) for k in range(20)])
+    cold = {"steps": 20, "flush_read_bytes": 512 << 20,
+            "step_ms_median": round(float(np.median(cold_step)), 5),
+            "step_ms_min": round(float(cold_step.min()), 5),
+            "stages_ms_median": {n: round(float(v), 5) for n, v in
+                                 zip(("bin", "idw_nn", "bilinear"), np.median(cold_stage, axis=0))}}
+    log(f"cold steps (512 MiB read before each): median {cold['step_ms_median']:.4f} ms, "
+        f"stages {cold['stages_ms_median']}")
 
     # next row: Catmull-Rom 2x of the same grid (not part of the step)
     cub = torch.empty_like(up)
@@ -694,6 +750,13 @@ def main():
                    "n_binned": int(n_binned)},
         "stages_ms": {"bin": round(float(st_ms[0]), 5), "idw_nn": round(float(st_ms[1]), 5),
                       "bilinear": round(float(st_ms[2]), 5)},
+        "step_ms_events": {"median": round(float(np.median(step_ev)), 5),
+                           "min": round(float(step_ev.min()), 5)},
+        "cache": "timed steps run back to back: the step writes 268 MB of bilinear output, "
+                 "more than the 256 MB last-level cache, but part of its inputs can stay "
+                 "resident; `cold` repeats the step after a 512 MiB read",
+        "cold": cold,
+        "nan_frac": round(nan_frac, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "precision_utm": precision,
