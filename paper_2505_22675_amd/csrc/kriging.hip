@@ -37,7 +37,7 @@ namespace auv {
 namespace {
 
 constexpr int kKrigCols = 256;    // destination columns per block (one per thread)
-constexpr int kKrigRows = 8;      // destination rows per block
+constexpr int kKrigRows = 16;     // destination rows per block
 constexpr int kKrigStage = 6144;  // source values staged in LDS
 constexpr int kBlockFloats = 10 * 9 + 6 * 6 + 6 * 6 + 4 * 4;
 constexpr double kMaxRangeSpacings = 1e4;  // the FP64 inverse stays well conditioned
@@ -147,7 +147,44 @@ __global__ __launch_bounds__(kKrigCols) void k_kriging(const KrigArgs p)
                 ex2[i] = e * e * p.c2;
             }
         }
+        // the node's 25 covariance terms depend only on its offsets in the
+        // window: x is fixed for the thread's column and rows cycle through a
+        // few y offsets (two at a 2x resample), so the terms of the last two
+        // offsets are kept and reused when a row's offset recurs
+        float ca[25], cb[25];
+        float dva = NAN, dvb = NAN;
+        bool fill_a = true;
+        auto terms = [&](float (&e)[25], float dv) {
+    #pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const float ey = ((float)k - dv) * p.fdy;
+                const float ey2 = ey * ey * p.c2;
+    #pragma unroll
+                for (int i = 0; i < 5; ++i) {
+                    const float t = __builtin_amdgcn_sqrtf(ex2[i] + ey2);
+                    if constexpr (kSeries) {
+                        // 1 - exp(-t) = t (1 - t/2 (1 - t/3 (... (1 - t/7))))
+                        float g = fmaf(-t, 1.0f / 7.0f, 1.0f);
+                        g = fmaf(-t * (1.0f / 6.0f), g, 1.0f);
+                        g = fmaf(-t * (1.0f / 5.0f), g, 1.0f);
+                        g = fmaf(-t * (1.0f / 4.0f), g, 1.0f);
+                        g = fmaf(-t * (1.0f / 3.0f), g, 1.0f);
+                        g = fmaf(-t * 0.5f, g, 1.0f);
+                        e[k * 5 + i] = t * g;
+                    } else {
+                        e[k * 5 + i] = __builtin_amdgcn_exp2f(-t);
+                    }
+                }
+            }
+        };
         float w[26];
+        auto dot = [&](const float (&e)[25]) {
+            float acc = 0.0f;
+    #pragma unroll
+            for (int q = 0; q < 25; ++q)
+                acc = fmaf(e[q], w[q], acc);
+            return acc;
+        };
         float zc = 0.0f;
         bool bad = false;
         int cur = -1;  // window row start of w (the same for every thread of the block)
@@ -266,27 +303,21 @@ __global__ __launch_bounds__(kKrigCols) void k_kriging(const KrigArgs p)
                 v = top + s * (bot - top);
             } else {
                 const float dv = s_dv[r];
-                float acc = 0.0f;
-    #pragma unroll
-                for (int k = 0; k < 5; ++k) {
-                    const float e = ((float)k - dv) * p.fdy;
-                    const float ey2 = e * e * p.c2;
-    #pragma unroll
-                    for (int i = 0; i < 5; ++i) {
-                        const float t = __builtin_amdgcn_sqrtf(ex2[i] + ey2);
-                        if constexpr (kSeries) {
-                            // 1 - exp(-t) = t (1 - t/2 (1 - t/3 (... (1 - t/7))))
-                            float g = fmaf(-t, 1.0f / 7.0f, 1.0f);
-                            g = fmaf(-t * (1.0f / 6.0f), g, 1.0f);
-                            g = fmaf(-t * (1.0f / 5.0f), g, 1.0f);
-                            g = fmaf(-t * (1.0f / 4.0f), g, 1.0f);
-                            g = fmaf(-t * (1.0f / 3.0f), g, 1.0f);
-                            g = fmaf(-t * 0.5f, g, 1.0f);
-                            acc = fmaf(t * g, w[k * 5 + i], acc);
-                        } else {
-                            acc = fmaf(__builtin_amdgcn_exp2f(-t), w[k * 5 + i], acc);
-                        }
-                    }
+                float acc;
+                if (dv == dva) {
+                    acc = dot(ca);
+                } else if (dv == dvb) {
+                    acc = dot(cb);
+                } else if (fill_a) {
+                    terms(ca, dv);
+                    dva = dv;
+                    fill_a = false;
+                    acc = dot(ca);
+                } else {
+                    terms(cb, dv);
+                    dvb = dv;
+                    fill_a = true;
+                    acc = dot(cb);
                 }
                 v = kSeries ? zc + (w[25] + acc) : zc + (w[25] - acc);
             }
