@@ -37,7 +37,7 @@ namespace auv {
 namespace {
 
 constexpr int kKrigCols = 256;    // destination columns per block (one per thread)
-constexpr int kKrigRows = 16;     // destination rows per block
+constexpr int kKrigRows = 32;     // destination rows per block
 constexpr int kKrigStage = 6144;  // source values staged in LDS
 constexpr int kBlockFloats = 10 * 9 + 6 * 6 + 6 * 6 + 4 * 4;
 constexpr double kMaxRangeSpacings = 1e4;  // the FP64 inverse stays well conditioned
