@@ -171,9 +171,13 @@ def _median_ms(fn, stream, reps):
 
 def _cpu_median_ms(fn):
     """Median wall time of fn() in ms over up to five runs (fewer once a second
-    has been spent; at least one), after one untimed run that starts the host
-    thread pool."""
-    fn()
+    has been spent; at least one), after untimed runs (up to 20, or 0.2 s) that
+    start and settle the host thread pool."""
+    w0 = time.perf_counter()
+    for _ in range(20):
+        fn()
+        if time.perf_counter() - w0 > 0.2:
+            break
     times = []
     while len(times) < 5 and (not times or sum(times) < 1.0):
         c0 = time.perf_counter()

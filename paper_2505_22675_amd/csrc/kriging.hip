@@ -37,7 +37,7 @@ namespace auv {
 namespace {
 
 constexpr int kKrigCols = 256;    // destination columns per block (one per thread)
-constexpr int kKrigRows = 32;     // destination rows per block
+constexpr int kKrigRows = 32;     // destination rows per block, at most
 constexpr int kKrigStage = 6144;  // source values staged in LDS
 constexpr int kBlockFloats = 10 * 9 + 6 * 6 + 6 * 6 + 4 * 4;
 constexpr double kMaxRangeSpacings = 1e4;  // the FP64 inverse stays well conditioned
@@ -50,6 +50,7 @@ struct KrigArgs {
     int snx, sny, dnx, dny;
     float fdx, fdy;  // source spacing
     float c2;        // (log2(e) / range)^2, or (1 / range)^2 for the series form
+    int rows;        // destination rows per block (8 .. kKrigRows)
     // the diagonal blocks of K^-1 in the mirror basis, row-major: even-even
     // 10 x 9 (rows: 9 nodes and the unbiasedness entry; its column is never
     // used since the data vector has a zero there), even-odd 6 x 6, odd-even
@@ -89,9 +90,9 @@ __global__ __launch_bounds__(kKrigCols) void k_kriging(const KrigArgs p)
     __shared__ float s_dv[kKrigRows], s_s[kKrigRows];
     __shared__ float s_src[kKrigStage];
     const int col0 = blockIdx.x * kKrigCols;
-    const int row0 = blockIdx.y * kKrigRows;
+    const int row0 = blockIdx.y * p.rows;
     const int ncol = min(kKrigCols, p.dnx - col0);
-    const int nrow = min(kKrigRows, p.dny - row0);
+    const int nrow = min(p.rows, p.dny - row0);
     {
         const int c = threadIdx.x;
         const Axis a = axis_of(p.dx0, p.ddx, min(col0 + c, p.dnx - 1), p.sx0, p.sdx, p.snx);
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(kKrigCols) void k_kriging(const KrigArgs p)
         s_i1[c] = a.i1;
         s_t[c] = a.t;
     }
-    if (threadIdx.x < kKrigRows) {
+    if (threadIdx.x < p.rows) {
         const int r = threadIdx.x;
         const Axis a = axis_of(p.dy0, p.ddy, min(row0 + r, p.dny - 1), p.sy0, p.sdy, p.sny);
         const int wy = window_start(a.u, p.sny);
@@ -526,8 +527,13 @@ auv_status launch_kriging(const float *src, const auv_grid_desc &s, float *dst,
         return fail(AUV_ERR_INVALID, "singular kriging system for this spacing and range");
     if (!mirror_blocks(kinv, p.mb))
         return fail(AUV_ERR_INVALID, "kriging inverse lost its mirror symmetry (range far outside the node spacing)");
-    const dim3 grid((unsigned)((d.nx + kKrigCols - 1) / kKrigCols),
-                    (unsigned)((d.ny + kKrigRows - 1) / kKrigRows));
+    // more rows per block reuse more covariance terms, but a small grid needs
+    // the blocks: halve from kKrigRows (down to 8) while under 1024 blocks
+    const int64_t ncb = (d.nx + kKrigCols - 1) / kKrigCols;
+    p.rows = kKrigRows;
+    while (p.rows > 8 && ncb * ((d.ny + p.rows - 1) / p.rows) < 1024)
+        p.rows /= 2;
+    const dim3 grid((unsigned)ncb, (unsigned)((d.ny + p.rows - 1) / p.rows));
     if (series)
         k_kriging<true><<<grid, kKrigCols, 0, st>>>(p);
     else
