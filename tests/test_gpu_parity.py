@@ -538,6 +538,40 @@ def test_kriging_rejects_bad_range(ag):
             ag.auv_resample_kriging(src, g, dst, g, r)
 
 
+@pytest.mark.parametrize("range_cells", [3.0, 1000.0])
+def test_kriging_ragged_tall_blocks(ag, orc, range_cells):
+    """2x kriging of a 2048 x 1100 grid to 4096 x 2200: enough blocks for 32
+    rows per block, so the last block holds 24 rows; sampled rows (the last
+    26, the first 4, a few inside) against the oracle on a band of source rows
+    that holds each row's windows without moving them.  The long range takes
+    the series form of the covariance terms."""
+    from gen import GridSpec
+    sh, sw = 1100, 2048
+    rng = np.random.default_rng(int(range_cells))
+    v = (-5000.0 + rng.normal(0, 400.0, (sh, sw))).astype(np.float32)
+    v[rng.random((sh, sw)) < 0.002] = np.nan
+    sg = GridSpec(1000.0, 2000.0, 2.0, 2.0, sw, sh)
+    dg = GridSpec(1000.0, 2000.0, 1.0, 1.0, 2 * sw, 2 * sh)
+    rng_m = range_cells * sg.dx
+    src = torch.from_numpy(v).cuda()
+    dst = torch.empty((dg.ny, dg.nx), dtype=torch.float32, device="cuda")
+    ag.auv_resample_kriging(src, sg, dst, dg, rng_m)
+    torch.cuda.synchronize()
+    out = dst.cpu().numpy()
+    rows = list(range(dg.ny - 26, dg.ny)) + [0, 1, 2, 3, 31, 32, 33, 1000, 1601]
+    for r in rows:
+        band_lo = max(0, r // 2 - 4)
+        band_hi = min(sh, r // 2 + 5)
+        sub = GridSpec(sg.x0, sg.y0 + band_lo * sg.dy, sg.dx, sg.dy, sw, band_hi - band_lo)
+        drow = GridSpec(dg.x0, dg.y0 + float(r), 1.0, 1.0, dg.nx, 1)
+        ref = orc.kriging(_ogrid(orc, sub), v[band_lo:band_hi].astype(np.float64),
+                          _ogrid(orc, drow), rng_m)[0]
+        o = out[r].astype(np.float64)
+        assert np.array_equal(np.isnan(o), np.isnan(ref)), f"row {r}"
+        ok = ~np.isnan(ref)
+        assert np.max(np.abs(o[ok] - ref[ok]) / np.abs(ref[ok])) <= REL, f"row {r}"
+
+
 def test_kriging_cfg2_upsample(ag, orc, cfg2_run):
     """2x kriging resample of the full cfg2 IDW grid (holes included) to
     8192^2 at 1 m, sampled rows against the oracle on a band of source rows
