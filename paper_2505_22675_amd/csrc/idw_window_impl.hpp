@@ -16,7 +16,7 @@
 //
 // Exactness as in the tile kernel: membership, ranking and hits on the exact
 // lattice D^2 (64-bit integers), FP32 distances/weights from lattice offsets
-// plus residuals, FP32 final quotient.  Sums are relative to one
+// plus residuals, FP64 final quotient.  Sums are relative to one
 // reference depth per tile (a sounding's depth, so a constant field stays
 // exact).  A hit (D^2 == 0) enters with a dominant weight, which yields the
 // mean of the hits; it is recognised at the end by a best key of D^2 == 0.
@@ -835,10 +835,10 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                     // ratio is the mean of the hits, and it beats min_pts
                     const bool hole = cnt == 0 || (cnt < a.min_pts && !hit);
                     const float2 nd = s_nd[q];
-                    // FP32 quotient by the hardware reciprocal: a few ulp of the
-                    // offset from the tile's reference depth (1e-7 relative or
-                    // better at bathymetric depths)
-                    a.z_out[o] = hole ? NAN : zref + nd.x * __builtin_amdgcn_rcpf(nd.y);
+                    // the quotient and the return to absolute depth in FP64,
+                    // rounded once to FP32
+                    a.z_out[o] = hole ? NAN
+                                      : (float)((double)zref + (double)nd.x / (double)nd.y);
                 }
             }
             unsigned long long om = __ballot(over);
