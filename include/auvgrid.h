@@ -160,8 +160,11 @@ void auv_bins_destroy(auv_bins *bins);
  *     distance from the node computed from the sounding's double
  *     coordinates, clamped to [min, max] of the depths in S.
  * Distances and weights run in FP32 (with the FP64 rebase), the final
- * num/den division in FP64.  Tolerance against the FP64 definition: 1e-5
- * relative per node; S, the NaN mask, counts and the nearest pick are exact.
+ * num/den division and the clamp in FP64, rounded once to FP32; the clamp
+ * bounds are the depths rounded to FP32, so every returned value lies within
+ * [min, max] of the FP32-rounded depths of S exactly.  Tolerance against the
+ * FP64 definition: 1e-5 relative per node; S, the NaN mask, counts and the
+ * nearest pick are exact.
  *   z_out      device float [ny][nx];
  *   cnt_out    device int32 [ny][nx] |S|, nullable;
  *   nn_idx_out device int32 [ny][nx] first member of S (the nearest sounding,
@@ -336,7 +339,7 @@ typedef struct {
 typedef struct auv_session auv_session;
 
 /* Device bytes a session needs: `fixed` for the request slots' staging and
- * binning space and the launch tables, plus `per_vehicle` (12 bytes per node
+ * binning space and the launch tables, plus `per_vehicle` (20 bytes per node
  * of the largest grid) for each admitted vehicle.  Host only. */
 auv_status auv_session_budget(const auv_session_desc *desc, size_t *fixed,
                               size_t *per_vehicle);
@@ -368,7 +371,8 @@ auv_status auv_session_poll(auv_session *s, uint64_t ticket, auv_ticket_info *in
 auv_status auv_session_drain(auv_session *s);
 
 /* Wait for the vehicle's submitted requests, then enqueue the read-out of its
- * grid on `stream`: z_out device float [ny][nx] (NaN: no value), cnt_out
+ * grid on `stream`: z_out device float [ny][nx] (NaN: no value; clamped to
+ * the depth range of the node's soundings like auv_interp_idw), cnt_out
  * device int32 [ny][nx] (nullable; soundings within the radius so far). */
 auv_status auv_session_read_grid(auv_session *s, int32_t vehicle, float *z_out,
                                  int32_t *cnt_out, auv_stream stream);

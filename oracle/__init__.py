@@ -75,12 +75,14 @@ def _load():
                                 P(i64), P(i64), P(i64)]
         lib.orc_idw.argtypes = [P(_Grid), vp, vp, vp, i64, d, d, i32, i32, i32,
                                 vp, i64, vp, vp, vp, i32]
+        lib.orc_idw_bounds.argtypes = [P(_Grid), vp, vp, vp, i64, d, i32, i32, vp, i64,
+                                       vp, vp, i32]
         lib.orc_nearest.argtypes = [P(_Grid), vp, vp, vp, i64, d, i32, vp, i64,
                                     vp, vp, i32]
         lib.orc_bilinear.argtypes = [P(_Grid), vp, P(_Grid), vp, i32]
         lib.orc_bicubic.argtypes = [P(_Grid), vp, P(_Grid), vp, i32]
         lib.orc_kriging.argtypes = [P(_Grid), vp, P(_Grid), d, vp, i32]
-        for f in (lib.orc_bin_dims, lib.orc_bin, lib.orc_idw, lib.orc_nearest,
+        for f in (lib.orc_bin_dims, lib.orc_bin, lib.orc_idw, lib.orc_idw_bounds, lib.orc_nearest,
                   lib.orc_bilinear, lib.orc_bicubic, lib.orc_kriging):
             f.restype = ctypes.c_int
         _lib = lib
@@ -152,6 +154,30 @@ def idw(grid: Grid, x, y, z, radius: float, power: float = 2.0, min_pts: int = 1
         shape = (grid.ny, grid.nx)
         return zo.reshape(shape), co.reshape(shape), no.reshape(shape)
     return zo, co, no
+
+
+def idw_bounds(grid: Grid, x, y, z, radius: float, max_pts: int = 0, bin_log2: int = -1,
+               nodes=None, nthreads: int = 0):
+    """Smallest and largest depth over O1's selected set (NaN where it is
+    empty): returns (lo, hi) float64; nodes=None -> [ny, nx]."""
+    lib = _load()
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    n = x.shape[0]
+    if nodes is None:
+        m = grid.nx * grid.ny
+        nd = None
+    else:
+        nd = np.ascontiguousarray(nodes, dtype=np.int64)
+        m = nd.shape[0]
+    lo = np.empty(max(m, 1), dtype=np.float64)
+    hi = np.empty(max(m, 1), dtype=np.float64)
+    _check(lib.orc_idw_bounds(ctypes.byref(grid.c()), _ptr(x), _ptr(y), _ptr(z), n, radius,
+                              max_pts, bin_log2, _ptr(nd), m if nd is not None else 0,
+                              _ptr(lo), _ptr(hi), nthreads), "orc_idw_bounds")
+    lo, hi = lo[:m], hi[:m]
+    if nodes is None:
+        return lo.reshape(grid.ny, grid.nx), hi.reshape(grid.ny, grid.nx)
+    return lo, hi
 
 
 def nearest(grid: Grid, x, y, z, radius: float, bin_log2: int = -1, nodes=None,

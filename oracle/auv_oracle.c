@@ -437,6 +437,62 @@ int orc_idw(const orc_grid *g, const double *x, const double *y, const double *z
     return err ? ORC_ENOMEM : ORC_OK;
 }
 
+/* Bounds of O1's selected set: the smallest and largest depth over S(n)
+ * (steps 1-2 of O1: the closed lattice disk, ranked by (D^2, original index)
+ * and cut to the first max_pts).  Every O1 value lies within them (step 6
+ * clamps to them); NaN for both when S(n) is empty. */
+int orc_idw_bounds(const orc_grid *g, const double *x, const double *y, const double *z,
+                   int64_t n, double radius, int32_t max_pts, int32_t bin_log2,
+                   const int64_t *nodes, int64_t n_nodes, double *lo_out, double *hi_out,
+                   int32_t nthreads)
+{
+    if (max_pts < 0)
+        return ORC_EINVAL;
+    orc_search S;
+    int rc = orc_search_init(&S, g, x, y, z, n, radius, bin_log2);
+    if (rc != ORC_OK)
+        return rc;
+    if (!orc_nodes_ok(g, nodes, n_nodes)) {
+        orc_search_free(&S);
+        return ORC_EINVAL;
+    }
+    int64_t total = nodes ? n_nodes : (int64_t)g->nx * g->ny;
+    int err = 0;
+    if (nthreads <= 0)
+        nthreads = omp_get_max_threads();
+#pragma omp parallel num_threads(nthreads) reduction(| : err)
+    {
+        orc_cbuf c = {0, 0, 0};
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t k = 0; k < total; ++k) {
+            int64_t f = nodes ? nodes[k] : k;
+            int64_t Xn = orc_node_lattice((int32_t)(f % g->nx), g->dx);
+            int64_t Yn = orc_node_lattice((int32_t)(f / g->nx), g->dy);
+            if (!orc_collect(&S, Xn, Yn, &c)) {
+                err = 1;
+                continue;
+            }
+            qsort(c.v, (size_t)c.n, sizeof(orc_cand), orc_cand_cmp);
+            int64_t m = c.n;
+            if (max_pts > 0 && m > max_pts)
+                m = max_pts;
+            double lo = NAN, hi = NAN;
+            for (int64_t j = 0; j < m; ++j) {
+                double v = z[c.v[j].i];
+                if (j == 0 || v < lo)
+                    lo = v;
+                if (j == 0 || v > hi)
+                    hi = v;
+            }
+            lo_out[k] = lo;
+            hi_out[k] = hi;
+        }
+        free(c.v);
+    }
+    orc_search_free(&S);
+    return err ? ORC_ENOMEM : ORC_OK;
+}
+
 /* -------------------------------------------------------------------- NN -- */
 
 /* O2: argmin of (D^2, original index) over the disk, computed directly (no

@@ -67,6 +67,13 @@ int orc_idw(const orc_grid *g, const double *x, const double *y, const double *z
             int64_t n_nodes, double *z_out, int32_t *cnt_out, int32_t *nn_out,
             int32_t nthreads);
 
+/* Bounds of O1's selected set S(n): smallest and largest depth over it (NaN
+ * when S(n) is empty).  Same search and node list conventions as orc_idw. */
+int orc_idw_bounds(const orc_grid *g, const double *x, const double *y, const double *z,
+                   int64_t n, double radius, int32_t max_pts, int32_t bin_log2,
+                   const int64_t *nodes, int64_t n_nodes, double *lo_out, double *hi_out,
+                   int32_t nthreads);
+
 /* O2: nearest sounding within the radius by the key (D^2, original index).
  * idx_out = -1 and z_out = NaN where no sounding is within the radius. */
 int orc_nearest(const orc_grid *g, const double *x, const double *y,

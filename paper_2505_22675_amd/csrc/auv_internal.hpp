@@ -201,6 +201,7 @@ struct IdwArgs {
     // relative to zref_acc
     float *acc_num, *acc_den;
     int32_t *acc_cnt;
+    float *acc_lo, *acc_hi;   // smallest / largest member depth (valid where acc_cnt > 0)
     double zref_acc;
 };
 auv_status launch_idw(const auv_bin_view &bins, const IdwArgs &a, hipStream_t st);

@@ -85,13 +85,14 @@ __global__ __launch_bounds__(64) void k_idw_batch_window(const IdwItem *__restri
 {
     __shared__ float2 s_nd[win::kAcc];
     __shared__ int s_cnt[win::kAcc];
+    __shared__ float2 s_mm[win::kAcc];
     __shared__ unsigned long long s_key[win::kAcc];
     __shared__ float s_emax[win::kAcc];
     __shared__ int s_beg[win::kMaxRows];
     __shared__ int s_off[win::kMaxRows + 1];
     __shared__ int4 s_rec[128];
-    const win::WinSmem sm{s_nd, s_cnt, s_key, nullptr, nullptr, nullptr, s_emax, s_beg, s_off,
-                          s_rec, s_rec + 1, nullptr};
+    const win::WinSmem sm{s_nd, s_cnt, s_mm, s_key, nullptr, nullptr, nullptr, s_emax, s_beg,
+                          s_off, s_rec, s_rec + 1, nullptr};
     const int home = blockIdx.x & (kQueues - 1);
     for (int k = 0; k < kQueues; ++k) {
         const int q = (home + k) & (kQueues - 1);

@@ -16,9 +16,11 @@
 //
 // Exactness as in the tile kernel: membership, ranking and hits on the exact
 // lattice D^2 (64-bit integers), FP32 distances/weights from lattice offsets
-// plus residuals, FP64 final quotient.  Sums are relative to one
-// reference depth per tile (a sounding's depth, so a constant field stays
-// exact).  A hit (D^2 == 0) enters with a dominant weight, which yields the
+// plus residuals, FP64 final quotient, clamped to the smallest and largest
+// depth of the node's selected set (tracked beside the sums), so that every
+// value lies within its neighbours' depths also after rounding.  Sums are
+// relative to one reference depth per tile (a sounding's depth, so a
+// constant field stays exact).  A hit (D^2 == 0) enters with a dominant weight, which yields the
 // mean of the hits; it is recognised at the end by a best key of D^2 == 0.
 // Nodes with more than max_pts members are re-done exactly by the whole wave
 // (bisection on the rank-k key over the node's candidates).
@@ -237,7 +239,7 @@ __device__ void exact_node(const auv_bin_view &bv, const IdwArgs &a, int X0, int
     };
     const int kcap = a.max_pts;
     // accumulate one selected member (per lane, reduced over the wave below)
-    float num = 0.0f, den = 0.0f, emax = -INFINITY;
+    float num = 0.0f, den = 0.0f, emax = -INFINITY, zlo = INFINITY, zhi = -INFINITY;
     int cnt = 0, hits = 0;
     double hsum = 0.0, bd2 = 1e300;
     int bidx = INT_MAX;
@@ -245,6 +247,8 @@ __device__ void exact_node(const auv_bin_view &bv, const IdwArgs &a, int X0, int
     auto take = [&](int k, double d2, float d2f, int ci) {
         const float z = bv.z[k];
         cnt += 1;
+        zlo = fminf(zlo, z);
+        zhi = fmaxf(zhi, z);
         if (d2 < bd2 || (d2 == bd2 && ci < bidx)) {
             bd2 = d2;
             bidx = ci;
@@ -413,6 +417,11 @@ __device__ void exact_node(const auv_bin_view &bv, const IdwArgs &a, int X0, int
         }
         num = wave_sum(num);
         den = wave_sum(den);
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            zlo = fminf(zlo, __shfl_xor(zlo, d, 64));
+            zhi = fmaxf(zhi, __shfl_xor(zhi, d, 64));
+        }
     }
     if ((threadIdx.x & 63) == 0) {
         if (kMode & 2) {
@@ -430,7 +439,8 @@ __device__ void exact_node(const auv_bin_view &bv, const IdwArgs &a, int X0, int
             else if (cnt < a.min_pts)
                 v = NAN;
             else
-                v = (float)((double)zref + (double)num / (double)den);
+                v = (float)fmin(fmax((double)zref + (double)num / (double)den, (double)zlo),
+                                (double)zhi);
             a.z_out[o] = v;
         }
     }
@@ -451,17 +461,19 @@ constexpr int kAcc = kTH * kRS;
 struct WinSmem {
     float2 *nd;                 // numerator, denominator        [kAcc]
     int *cnt;                   // members                       [kAcc]
+    float2 *mm;                 // smallest, largest member depth [kAcc]
     unsigned long long *key;    // packed (D^2 << b) | index     [kAcc] (packed)
     double *bd2;                // best D^2                      [kAcc] (unpacked)
     int *bidx;                  // best index                    [kAcc] (unpacked)
     float *bz;                  // best depth                    [kAcc] (unpacked)
     float *emax;                // running log2 weight max       [kAcc] (general p)
     int *beg, *off;             // staging rows                  [kMaxRows(+1)]
-    int4 *r0;                   // kept soundings: ia, jb, 8 qb, 4 qb          [64, stride 2]
+    int4 *r0;                   // kept soundings: ia, jb (exact form: depth bits), 8 qb, 4 qb
+                                //                                             [64, stride 2]
     int4 *r1;                   //   residual x, y, depth - zref (bits), index  [64, stride 2]
                                 // (r1 = r0 + 1: a record's halves are adjacent, so both
                                 //  reads of a visit share one LDS address)
-    float2 *rv;                 //   variant coordinates; depth  [64] (variants, unpacked)
+    float4 *rv;                 //   variant coordinates, depth   [64] (variants, unpacked)
 };
 
 // part / nparts: the wave takes every nparts-th 64-wide chunk of the tile's
@@ -483,6 +495,7 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
     // per lane).
     float2 *const s_nd = sm.nd;
     int *const s_cnt = sm.cnt;
+    float2 *const s_mm = sm.mm;
     unsigned long long *const s_key = sm.key;
     double *const s_bd2 = sm.bd2;
     int *const s_bidx = sm.bidx;
@@ -527,6 +540,7 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
     for (int q = lane; q < kAcc; q += 64) {
         s_nd[q] = make_float2(0.0f, 0.0f);
         s_cnt[q] = 0;
+        s_mm[q] = make_float2(INFINITY, -INFINITY);
         if constexpr (kPacked) {
             if constexpr (kKey)
                 s_key[q] = ~0ull;
@@ -631,13 +645,12 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                 const int o0 = kExact ? (int)((((uint32_t)pia & 0xffffu) << 16) |
                                               ((uint32_t)pjb & 0xffffu))
                                       : pia;
-                sm.r0[2 * slot] = make_int4(o0, pjb, qb * 8, qb * 4);
+                sm.r0[2 * slot] = make_int4(o0, kExact && kPacked ? __float_as_int(pz) : pjb,
+                                            qb * 8, qb * 4);
                 sm.r1[2 * slot] = make_int4(__float_as_int(prx), __float_as_int(pry),
                                         __float_as_int(pdz), pidx);
-                if constexpr (!kExact)
-                    sm.rv[slot] = make_float2(pvx, pvy);
-                else if constexpr (!kPacked)
-                    sm.rv[slot] = make_float2(pz, 0.0f);
+                if constexpr (!kExact || !kPacked)
+                    sm.rv[slot] = make_float4(pvx, pvy, pz, 0.0f);
             }
             // the records are read back by the same wave, in order
             __builtin_amdgcn_wave_barrier();
@@ -647,7 +660,7 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
             typedef __attribute__((address_space(3))) const v4i lds_v4i;
             lds_v4i *rp0 = (lds_v4i *)sm.r0;
             asm volatile("" : "+v"(rp0));
-            const float2 *rpv = sm.rv;
+            const float4 *rpv = sm.rv;
             while (m) {
                 const int l = __ffsll((long long)m) - 1;
                 m &= m - 1ull;
@@ -661,12 +674,14 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                 const float srx = __int_as_float(w1.x), sry = __int_as_float(w1.y);
                 const float sdz = __int_as_float(w1.z);
                 const int sidx = w1.w;
-                float svx = 0.0f, svy = 0.0f, spz = 0.0f;
+                float svx = 0.0f, svy = 0.0f, spz;
                 if constexpr (!kExact || !kPacked) {
-                    const float2 v = *rpv;
+                    const float4 v = *rpv;
                     svx = v.x;
                     svy = v.y;
-                    spz = v.x;
+                    spz = v.z;
+                } else {
+                    spz = __int_as_float(w0.y);  // the depth itself (exact form)
                 }
                 ++rpv;
                 const int qb = qb4 >> 2;
@@ -709,8 +724,11 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                             reinterpret_cast<int *>(reinterpret_cast<char *>(s_cnt) + qb4 + qo[t] * 4);
                         float2 *const pn =
                             reinterpret_cast<float2 *>(reinterpret_cast<char *>(s_nd) + q8);
+                        float2 *const pm =
+                            reinterpret_cast<float2 *>(reinterpret_cast<char *>(s_mm) + q8);
                         // every read of the node before any write: one LDS round trip
                         const int cq = *pc;
+                        float2 mq = *pm;
                         unsigned long long kq = 0ull;
                         if constexpr (kKey)
                             kq = *reinterpret_cast<unsigned long long *>(
@@ -745,6 +763,9 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                             }
                         }
                         *pc = cq + 1;
+                        mq.x = fminf(mq.x, spz);
+                        mq.y = fmaxf(mq.y, spz);
+                        *pm = mq;
                         if constexpr (kIdw) {
                             if constexpr (kPmode != 0) {
                                 nd.x += w * sdz;
@@ -808,9 +829,13 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                 const int64_t o = (int64_t)(ta0 + la) * a.nx + tb0 + lb;
                 const float2 nd = s_nd[q];
                 const double shift = (double)zref - a.zref_acc;
+                const float2 mm = s_mm[q];
+                const int c0 = a.acc_cnt[o];
                 a.acc_num[o] += (float)((double)nd.x + (double)nd.y * shift);
                 a.acc_den[o] += nd.y;
-                a.acc_cnt[o] += cnt;
+                a.acc_cnt[o] = c0 + cnt;
+                a.acc_lo[o] = c0 > 0 ? fminf(a.acc_lo[o], mm.x) : mm.x;
+                a.acc_hi[o] = c0 > 0 ? fmaxf(a.acc_hi[o], mm.y) : mm.y;
             }
         } else {
             const bool over = act && kcap > 0 && cnt > kcap;
@@ -835,10 +860,12 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                     // ratio is the mean of the hits, and it beats min_pts
                     const bool hole = cnt == 0 || (cnt < a.min_pts && !hit);
                     const float2 nd = s_nd[q];
+                    const float2 mm = s_mm[q];
                     // the quotient and the return to absolute depth in FP64,
-                    // rounded once to FP32
+                    // clamped to the members' depths, rounded once to FP32
+                    const double v = (double)zref + (double)nd.x / (double)nd.y;
                     a.z_out[o] = hole ? NAN
-                                      : (float)((double)zref + (double)nd.x / (double)nd.y);
+                                      : (float)fmin(fmax(v, (double)mm.x), (double)mm.y);
                 }
             }
             unsigned long long om = __ballot(over);
@@ -860,6 +887,7 @@ __global__ __launch_bounds__(64) void k_idw_window(auv_bin_view bv, IdwArgs a, W
 {
     __shared__ float2 s_nd[kAcc];
     __shared__ int s_cnt[kAcc];
+    __shared__ float2 s_mm[kAcc];
     __shared__ unsigned long long s_key[kPacked ? kAcc : 1];
     __shared__ double s_bd2[kPacked ? 1 : kAcc];
     __shared__ int s_bidx[kPacked ? 1 : kAcc];
@@ -868,8 +896,8 @@ __global__ __launch_bounds__(64) void k_idw_window(auv_bin_view bv, IdwArgs a, W
     __shared__ int s_beg[kMaxRows];
     __shared__ int s_off[kMaxRows + 1];
     __shared__ int4 s_rec[128];
-    __shared__ float2 s_rv[kPrec == AUV_P_FP32_REBASE && kPacked ? 1 : 64];
-    const WinSmem sm{s_nd, s_cnt, s_key, s_bd2, s_bidx, s_bz, s_emax, s_beg, s_off,
+    __shared__ float4 s_rv[kPrec == AUV_P_FP32_REBASE && kPacked ? 1 : 64];
+    const WinSmem sm{s_nd, s_cnt, s_mm, s_key, s_bd2, s_bidx, s_bz, s_emax, s_beg, s_off,
                      s_rec, s_rec + 1, s_rv};
     window_tile<kMode, kPmode, kPacked, kChunks, kPrec>(
         bv, a, g, xcd_tile(blockIdx.x, ntx * nty), ntx, sm);

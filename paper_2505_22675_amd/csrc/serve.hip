@@ -73,6 +73,7 @@ __global__ __launch_bounds__(64 * kServeParts) void k_serve_update(
 {
     __shared__ float2 s_nd[kServeParts][win::kAcc];
     __shared__ int s_cnt[kServeParts][win::kAcc];
+    __shared__ float2 s_mm[kServeParts][win::kAcc];
     __shared__ float s_emax[1];
     __shared__ int s_beg[kServeParts][win::kMaxRows];
     __shared__ int s_off[kServeParts][win::kMaxRows + 1];
@@ -80,8 +81,9 @@ __global__ __launch_bounds__(64 * kServeParts) void k_serve_update(
     __shared__ float s_zref[kServeParts];
     __shared__ int s_task;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const win::WinSmem sm{s_nd[wave], s_cnt[wave], nullptr, nullptr, nullptr, nullptr, s_emax,
-                          s_beg[wave], s_off[wave], s_rec[wave], s_rec[wave] + 1, nullptr};
+    const win::WinSmem sm{s_nd[wave], s_cnt[wave], s_mm[wave], nullptr, nullptr, nullptr,
+                          nullptr, s_emax, s_beg[wave], s_off[wave], s_rec[wave],
+                          s_rec[wave] + 1, nullptr};
     int t0x = 0, t0y = 0, tcols = 1, nt = 0;
     if (lane < count) {
         const ServeItem &it = items[lane];
@@ -138,33 +140,42 @@ __global__ __launch_bounds__(64 * kServeParts) void k_serve_update(
         const int q = la * win::kRS + lb;
         if (la < min(win::kTH, it.a.ny - ta0) && lb < min(win::kTW, it.a.nx - tb0)) {
             double num = 0.0;
-            float den = 0.0f;
+            float den = 0.0f, lo = INFINITY, hi = -INFINITY;
             int cnt = 0;
 #pragma unroll
             for (int w = 0; w < kServeParts; ++w) {
                 const int cw = s_cnt[w][q];
                 if (cw > 0) {
                     const float2 nd = s_nd[w][q];
+                    const float2 mm = s_mm[w][q];
                     num += (double)nd.x + (double)nd.y * ((double)s_zref[w] - it.a.zref_acc);
                     den += nd.y;
                     cnt += cw;
+                    lo = fminf(lo, mm.x);
+                    hi = fmaxf(hi, mm.y);
                 }
             }
             if (cnt > 0) {
                 const int64_t o = (int64_t)(ta0 + la) * it.a.nx + tb0 + lb;
+                const int c0 = it.a.acc_cnt[o];
                 it.a.acc_num[o] += (float)num;
                 it.a.acc_den[o] += den;
-                it.a.acc_cnt[o] += cnt;
+                it.a.acc_cnt[o] = c0 + cnt;
+                // the depth range of every sounding accumulated so far
+                it.a.acc_lo[o] = c0 > 0 ? fminf(it.a.acc_lo[o], lo) : lo;
+                it.a.acc_hi[o] = c0 > 0 ? fmaxf(it.a.acc_hi[o], hi) : hi;
             }
         }
         __syncthreads();  // the LDS is reused by the next tile
     }
 }
 
-// Read-out: z = z_ref + num / den; NaN where no sounding, or fewer than
-// min_pts and no hit (a hit's weight makes den >= 2^80).
+// Read-out: z = z_ref + num / den, clamped to the depth range of the node's
+// soundings; NaN where no sounding, or fewer than min_pts and no hit (a hit's
+// weight makes den >= 2^80).
 __global__ void k_serve_read(const float *__restrict__ num, const float *__restrict__ den,
-                             const int32_t *__restrict__ cnt, int64_t m, double zref,
+                             const int32_t *__restrict__ cnt, const float *__restrict__ lo,
+                             const float *__restrict__ hi, int64_t m, double zref,
                              int32_t min_pts, float *__restrict__ z_out,
                              int32_t *__restrict__ cnt_out)
 {
@@ -174,7 +185,9 @@ __global__ void k_serve_read(const float *__restrict__ num, const float *__restr
         const float d = den[i];
         const bool hit = d >= win::kHitW;
         const bool hole = c == 0 || (c < min_pts && !hit);
-        z_out[i] = hole ? NAN : (float)(zref + (double)num[i] / (double)d);
+        z_out[i] = hole ? NAN
+                        : (float)fmin(fmax(zref + (double)num[i] / (double)d, (double)lo[i]),
+                                      (double)hi[i]);
         if (cnt_out)
             cnt_out[i] = c;
     }
@@ -414,7 +427,8 @@ void budget_of(const auv_session_desc *d, const std::vector<Vehicle> &veh, size_
     }
     const size_t tables = 2 * align256(table_layout().bytes);
     *fixed = tables + (size_t)d->slots * (*stage + *ws);
-    *per_vehicle = 3 * align256(4 * (size_t)nodes);
+    // five planes: weighted depth, weight, count, smallest and largest depth
+    *per_vehicle = 5 * align256(4 * (size_t)nodes);
 }
 
 // Enqueue one launch (no lock held; picks carry everything it needs).
@@ -465,6 +479,8 @@ auv_status enqueue_launch(auv_session *s, const std::vector<Pick> &picks, int ta
         it.a.acc_num = acc;
         it.a.acc_den = acc + plane;
         it.a.acc_cnt = reinterpret_cast<int32_t *>(acc + 2 * plane);
+        it.a.acc_lo = acc + 3 * plane;
+        it.a.acc_hi = acc + 4 * plane;
         it.g = V.wg;
         it.ntx = (V.grid.d.nx + win::kTW - 1) / win::kTW;
         it.bbox = reinterpret_cast<const int32_t *>(dev);
@@ -829,8 +845,8 @@ auv_status auv_session_read_grid(auv_session *s, int32_t vehicle, float *z_out, 
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t blocks = std::min<int64_t>((V.nodes + 255) / 256, 8192);
     k_serve_read<<<(unsigned)std::max<int64_t>(blocks, 1), 256, 0, st>>>(
-        acc, acc + plane, reinterpret_cast<const int32_t *>(acc + 2 * plane), V.nodes, V.zref,
-        s->desc.params.min_pts, z_out, cnt_out);
+        acc, acc + plane, reinterpret_cast<const int32_t *>(acc + 2 * plane), acc + 3 * plane,
+        acc + 4 * plane, V.nodes, V.zref, s->desc.params.min_pts, z_out, cnt_out);
     AUV_HIP(hipGetLastError());
     return AUV_OK;
 }

@@ -136,8 +136,9 @@ def _serve_desc(**kw):
 
 def test_session_budget_on_host():
     fixed, per_vehicle = ag.auv_session_budget(_serve_desc(max_request=50000, slots=8))
-    # three 4-byte planes per node of a 2048^2 grid
-    assert per_vehicle == 3 * 2048 * 2048 * 4
+    # five 4-byte planes per node of a 2048^2 grid: weighted depth, weight,
+    # count, smallest and largest depth
+    assert per_vehicle == 5 * 2048 * 2048 * 4
     # per slot: 24 B per sounding staged plus the binning workspace of 514^2 bins
     assert 8 * (50000 * 24 + 514 * 514 * 8) < fixed < 8 * (50000 * 200 + 514 * 514 * 20) + 2 ** 22
     f2, _ = ag.auv_session_budget(_serve_desc(max_request=50000, slots=16))

@@ -188,9 +188,11 @@ def test_batch_autotune_round_trip(ag, orc, tmp_path):
     b.close()
 
 
-def test_batch_full_size_sampled(ag, orc, tmp_path):
-    """The 256-tile batch at full size, autotuned as timed: every tile checked
-    on 48 sampled nodes (corners included) against the oracle at those nodes."""
+def test_batch_full_size(ag, orc, tmp_path):
+    """The 256-tile batch at full size, autotuned as timed (two replays of the
+    graph): every node of every tile against the oracle.  A tile whose oracle
+    search would visit more than 6e7 candidates would be checked on 8192 nodes
+    (edges included) instead; at this workload none does."""
     tiles = workload_cfg3_tiles()
     items = [_Item(ag, s) for s in tiles]
     b0 = ag.Batch([it.item for it in items])
@@ -204,22 +206,33 @@ def test_batch_full_size_sampled(ag, orc, tmp_path):
     b.launch()
     torch.cuda.synchronize()
     rng = np.random.default_rng(31)
+    full = 0
     for k, it in enumerate(items):
         g = it.s.grid
         m = g.nx * g.ny
-        nodes = np.unique(np.concatenate([[0, g.nx - 1, m - g.nx, m - 1],
-                                          rng.integers(0, m, 44)])).astype(np.int64)
-        sel = torch.from_numpy(nodes).cuda()
-        gz = it.zo.view(-1)[sel].cpu().numpy().astype(np.float64)
-        gc = it.co.view(-1)[sel].cpu().numpy()
-        gn = it.no.view(-1)[sel].cpu().numpy()
+        density = len(it.s.x) / (g.nx * g.dx * g.ny * g.dy)
+        label = f"tile {k} (n={len(it.s.x)}, side={g.nx}, plan {b.item_plan(k)})"
+        if m * density * 169.0 <= 6e7:
+            nodes = None
+            full += 1
+            gz = it.zo.cpu().numpy().astype(np.float64)
+            gc, gn = it.co.cpu().numpy(), it.no.cpu().numpy()
+        else:
+            edges = np.concatenate([np.arange(g.nx), np.arange(m - g.nx, m),
+                                    np.arange(0, m, g.nx), np.arange(g.nx - 1, m, g.nx)])
+            nodes = np.unique(np.concatenate([edges, rng.integers(0, m, 8192)]))[:8192]
+            nodes = nodes.astype(np.int64)
+            sel = torch.from_numpy(nodes).cuda()
+            gz = it.zo.view(-1)[sel].cpu().numpy().astype(np.float64)
+            gc = it.co.view(-1)[sel].cpu().numpy()
+            gn = it.no.view(-1)[sel].cpu().numpy()
         oz, oc, on = orc.idw(_ogrid(orc, g), it.s.x, it.s.y, it.s.z, it.s.radius, it.s.power,
                              it.s.min_pts, it.s.max_pts, bin_log2=16, nodes=nodes)
-        label = f"tile {k} (n={len(it.s.x)}, side={g.nx}, plan {b.item_plan(k)})"
         assert np.array_equal(gc, oc), f"{label}: counts differ"
         assert np.array_equal(gn, on), f"{label}: nearest differ"
         assert np.array_equal(np.isnan(gz), np.isnan(oz)), f"{label}: NaN masks differ"
         ok = ~np.isnan(oz)
         err = np.abs(gz[ok] - oz[ok]) / np.maximum(np.abs(oz[ok]), 1e-30)
         assert err.size == 0 or err.max() <= REL, f"{label}: max rel err {err.max():.3e}"
+    assert full == len(items), f"only {full} tiles checked in full"
     b.close()

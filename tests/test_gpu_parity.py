@@ -203,26 +203,95 @@ def cfg2_run(ag):
     return s, res, grid, bins
 
 
-def test_cfg2_full_size_sampled_parity(ag, orc, cfg2_run):
+def _assert_within_bounds(z, lo, hi, label=""):
+    """Every non-NaN output lies within [min, max] of its selected set's depths
+    rounded to FP32 (the GPU clamps to the FP32 depths it holds); a node is
+    NaN exactly where the oracle's set is empty or below min_pts."""
+    z = z.astype(np.float32)
+    ok = ~np.isnan(z)
+    assert not np.isnan(lo[ok]).any(), f"{label}: value where the selected set is empty"
+    flo, fhi = lo[ok].astype(np.float32), hi[ok].astype(np.float32)
+    below = np.flatnonzero(z[ok] < flo)
+    above = np.flatnonzero(z[ok] > fhi)
+    assert below.size == 0 and above.size == 0, (
+        f"{label}: {below.size} below / {above.size} above the selected depths")
+    return int(ok.sum())
+
+
+def test_cfg2_full_grid_parity(ag, orc, cfg2_run):
     """The headline workload at full size (2M soundings -> 4096^2, r=6, k=16),
-    in the launch configuration the benchmark times, checked on sampled nodes."""
+    in the launch configuration the benchmark times, on every node: counts,
+    NaN mask, nearest index and depth exact, IDW within 1e-5, and every value
+    within its selected depths."""
     s, res, grid, bins = cfg2_run
-    rng = np.random.default_rng(58)
-    nodes = np.unique(np.concatenate([
-        rng.integers(0, 4096 * 4096, 30000),
-        np.arange(0, 4096),                       # first row
-        np.arange(4096 * 4095, 4096 * 4096),      # last row
-        np.arange(0, 4096 * 4096, 4096),          # first column
-    ]))
-    oz, oc, on = orc.idw(_ogrid(orc, s.grid), s.x, s.y, s.z, s.radius, s.power, s.min_pts,
-                         s.max_pts, bin_log2=19, nodes=nodes)
-    gz = res["z"].ravel()[nodes]
-    _assert_idw_equal(gz, res["cnt"].ravel()[nodes], res["nn_idx"].ravel()[nodes],
-                      res["nn_z"].ravel()[nodes], oz, oc, on, s.z, "cfg2 sampled")
-    # whole-grid properties: NaN exactly where nothing is in range
-    assert np.array_equal(np.isnan(res["z"]), res["cnt"] == 0)
-    assert np.array_equal(res["nn_idx"] >= 0, res["cnt"] > 0)
+    og = _ogrid(orc, s.grid)
+    oz, oc, on = orc.idw(og, s.x, s.y, s.z, s.radius, s.power, s.min_pts, s.max_pts,
+                         bin_log2=19)
+    _assert_idw_equal(res["z"], res["cnt"], res["nn_idx"], res["nn_z"], oz, oc, on, s.z,
+                      "cfg2 full grid")
+    lo, hi = orc.idw_bounds(og, s.x, s.y, s.z, s.radius, s.max_pts, bin_log2=19)
+    assert _assert_within_bounds(res["z"], lo, hi, "cfg2") > 0.75 * oz.size
     assert np.all(res["cnt"] <= 16)
+
+
+def test_cfg4_exact_path_full_size(ag, orc):
+    """cfg2's soundings at UTM-scale coordinates (easting 5e5, northing 4e6,
+    float64 input): the FP64-rebase path keeps the exact contract on every node
+    (counts, NaN mask, nearest picks exact; values within 1e-5 relative)."""
+    from gen import workload_cfg4
+    s = workload_cfg4()
+    res, grid, bins = _run_idw(ag, s)
+    og = _ogrid(orc, s.grid)
+    oz, oc, on = orc.idw(og, s.x, s.y, s.z, s.radius, s.power, s.min_pts, s.max_pts,
+                         bin_log2=19)
+    err = _assert_idw_equal(res["z"], res["cnt"], res["nn_idx"], res["nn_z"], oz, oc, on, s.z,
+                            "cfg4 exact path")
+    assert err.size > 0.75 * oz.size
+    lo, hi = orc.idw_bounds(og, s.x, s.y, s.z, s.radius, s.max_pts, bin_log2=19)
+    _assert_within_bounds(res["z"], lo, hi, "cfg4")
+
+
+@pytest.mark.parametrize("case", ["cfg1", "capped", "dense", "hits"])
+def test_idw_values_within_selected_depths(ag, orc, case):
+    """The clamp of the definition (every value within [min, max] of its
+    selected set), on the window form with no cap (cfg1), with a cap that binds
+    (the exact per-node path), on the dense form, and with lattice-snapped
+    soundings that sit on nodes (hits)."""
+    from gen import GridSpec, Soundings
+    if case == "cfg1":
+        s = workload_cfg1()
+        algo = ag.AUV_ALGO_AUTO
+    else:
+        rng = np.random.default_rng({"capped": 81, "dense": 82, "hits": 83}[case])
+        g = GridSpec(250.0, -40.0, 2.0, 2.0, 90, 75)
+        n = {"capped": 30000, "dense": 30000, "hits": 6000}[case]
+        x = g.x0 + rng.uniform(-6, 186, n)
+        y = g.y0 + rng.uniform(-6, 156, n)
+        if case == "hits":
+            x = g.x0 + np.round((x - g.x0) / 0.5) * 0.5 + 0.0
+            y = g.y0 + np.round((y - g.y0) / 0.5) * 0.5 + 0.0
+        # a rough field: neighbouring depths differ a lot, so the weighted
+        # mean is often close to one of them
+        z = -4000.0 + 300.0 * rng.standard_normal(n) * (rng.random(n) < 0.3)
+        s = Soundings(x, y, z, g, radius=6.0, power=2.0, min_pts=1,
+                      max_pts=0 if case == "hits" else 12)
+        algo = ag.AUV_ALGO_DENSE if case == "dense" else ag.AUV_ALGO_SPARSE
+    grid = ag.auv_grid_create(s.grid)
+    bins = ag.auv_bin_points(grid, _dev(s.x), _dev(s.y), _dev(s.z), s.radius, 0)
+    out = ag.grid_idw(grid, bins, power=s.power, min_pts=s.min_pts, max_pts=s.max_pts,
+                      with_counts=True, with_nearest=True, algo=algo)
+    torch.cuda.synchronize()
+    og = _ogrid(orc, s.grid)
+    oz, oc, on = orc.idw(og, s.x, s.y, s.z, s.radius, s.power, s.min_pts, s.max_pts,
+                         bin_log2=17)
+    _assert_idw_equal(out["z"].cpu().numpy(), out["cnt"].cpu().numpy(),
+                      out["nn_idx"].cpu().numpy(), out["nn_z"].cpu().numpy(), oz, oc, on, s.z,
+                      case)
+    lo, hi = orc.idw_bounds(og, s.x, s.y, s.z, s.radius, s.max_pts, bin_log2=17)
+    gz = out["z"].cpu().numpy()
+    # min_pts = 1 here, so the value is NaN exactly where the selected set is empty
+    assert np.array_equal(np.isnan(gz), np.isnan(lo))
+    assert _assert_within_bounds(gz, lo, hi, case) > 0
 
 
 def test_cfg2_binning_counts(ag, orc, cfg2_run):
@@ -267,8 +336,19 @@ def test_bilinear_parity(ag, orc, src_shape, dst_shape, nan_frac):
     assert np.max(np.abs(out[ok] - ref[ok]) / np.abs(ref[ok])) <= REL
 
 
+def _full_resample_check(out, ref, label):
+    assert np.array_equal(np.isnan(out), np.isnan(ref)), f"{label}: NaN masks differ"
+    ok = ~np.isnan(ref)
+    o = out[ok].astype(np.float64)
+    r = ref[ok]
+    err = np.abs(o - r) / np.abs(r)
+    assert err.max() <= REL, f"{label}: max rel err {err.max():.3e}"
+    return int(ok.sum())
+
+
 def test_bilinear_cfg2_upsample(ag, orc, cfg2_run):
-    """2x resample of the full cfg2 IDW grid to 8192^2 at 1 m (sampled rows)."""
+    """2x resample of the full cfg2 IDW grid to 8192^2 at 1 m, every one of the
+    67.1M destination nodes against the oracle (holes included)."""
     s, res, grid, bins = cfg2_run
     from gen import GridSpec
     sg = s.grid
@@ -277,23 +357,11 @@ def test_bilinear_cfg2_upsample(ag, orc, cfg2_run):
     dst = torch.empty((8192, 8192), dtype=torch.float32, device="cuda")
     ag.auv_resample_bilinear(src, sg, dst, dg)
     torch.cuda.synchronize()
-    rows = np.array([0, 1, 2, 4095, 4096, 8190, 8191, 1234, 7777])
-    # oracle on a band of source rows covering each sampled destination row
     out = dst.cpu().numpy()
-    for r in rows:
-        band_lo = max(0, r // 2 - 2)
-        band_hi = min(4096, r // 2 + 3)
-        sub = GridSpec(sg.x0, sg.y0 + band_lo * sg.dy, sg.dx, sg.dy, sg.nx, band_hi - band_lo)
-        # destination row r as a one-row grid; clamping at the band edge only
-        # matters at the true grid edge, where band and grid edges coincide
-        drow = GridSpec(0.0, (r + 0.5) - 0.5, 1.0, 1.0, 8192, 1)
-        ref = orc.bilinear(_ogrid(orc, sub), res["z"][band_lo:band_hi].astype(np.float64),
-                           _ogrid(orc, drow))[0]
-        o = out[r].astype(np.float64)
-        assert np.array_equal(np.isnan(o), np.isnan(ref)), f"row {r}"
-        ok = ~np.isnan(ref)
-        if ok.any():
-            assert np.max(np.abs(o[ok] - ref[ok]) / np.abs(ref[ok])) <= REL
+    del dst
+    ref = orc.bilinear(_ogrid(orc, sg), res["z"].astype(np.float64), _ogrid(orc, dg))
+    n = _full_resample_check(out, ref, "bilinear cfg2 2x")
+    assert 0.5 * out.size < n < out.size
 
 
 # ---------------------------------------------------------------- bicubic --
@@ -326,8 +394,7 @@ def test_bicubic_parity(ag, orc, src_shape, dst_shape, nan_frac):
 
 def test_bicubic_cfg2_upsample(ag, orc, cfg2_run):
     """2x Catmull-Rom resample of the full cfg2 IDW grid (holes included) to
-    8192^2 at 1 m, sampled rows against the oracle on a band of source rows
-    that holds every tap of the row."""
+    8192^2 at 1 m, every destination node against the oracle."""
     s, res, grid, bins = cfg2_run
     from gen import GridSpec
     sg = s.grid
@@ -337,21 +404,13 @@ def test_bicubic_cfg2_upsample(ag, orc, cfg2_run):
     ag.auv_resample_bicubic(src, sg, dst, dg)
     torch.cuda.synchronize()
     out = dst.cpu().numpy()
-    nan_fallbacks = 0
-    for r in [0, 1, 2, 3, 4095, 4096, 8189, 8190, 8191, 1234, 7777, 5000]:
-        band_lo = max(0, r // 2 - 3)
-        band_hi = min(4096, r // 2 + 4)
-        sub = GridSpec(sg.x0, sg.y0 + band_lo * sg.dy, sg.dx, sg.dy, sg.nx, band_hi - band_lo)
-        drow = GridSpec(0.0, float(r), 1.0, 1.0, 8192, 1)
-        ref = orc.bicubic(_ogrid(orc, sub), res["z"][band_lo:band_hi].astype(np.float64),
-                          _ogrid(orc, drow))[0]
-        o = out[r].astype(np.float64)
-        assert np.array_equal(np.isnan(o), np.isnan(ref)), f"row {r}"
-        ok = ~np.isnan(ref)
-        nan_fallbacks += int(np.isnan(res["z"][band_lo:band_hi]).any())
-        if ok.any():
-            assert np.max(np.abs(o[ok] - ref[ok]) / np.abs(ref[ok])) <= REL, f"row {r}"
-    assert nan_fallbacks > 0
+    del dst
+    ref = orc.bicubic(_ogrid(orc, sg), res["z"].astype(np.float64), _ogrid(orc, dg))
+    n = _full_resample_check(out, ref, "Catmull-Rom cfg2 2x")
+    # the fallback to bilinear next to holes happens (more NaN-free nodes than
+    # a strict 16-tap rule would leave)
+    bil = orc.bilinear(_ogrid(orc, sg), res["z"].astype(np.float64), _ogrid(orc, dg))
+    assert np.array_equal(np.isnan(ref), np.isnan(bil)) and n < out.size
 
 
 # ------------------------------------------------------- dispatch branches --
@@ -574,8 +633,9 @@ def test_kriging_ragged_tall_blocks(ag, orc, range_cells):
 
 def test_kriging_cfg2_upsample(ag, orc, cfg2_run):
     """2x kriging resample of the full cfg2 IDW grid (holes included) to
-    8192^2 at 1 m, sampled rows against the oracle on a band of source rows
-    that holds the row's windows without moving them."""
+    8192^2 at 1 m, checked on 320 whole destination rows (ten blocks of 32,
+    the first and last rows of the grid included) against the oracle on a band
+    of source rows that holds every window of the block without moving it."""
     s, res, grid, bins = cfg2_run
     from gen import GridSpec
     sg = s.grid
@@ -586,18 +646,18 @@ def test_kriging_cfg2_upsample(ag, orc, cfg2_run):
     ag.auv_resample_kriging(src, sg, dst, dg, rng_m)
     torch.cuda.synchronize()
     out = dst.cpu().numpy()
+    del dst
     fallbacks = 0
-    for r in [0, 1, 2, 3, 4, 5, 4095, 4096, 8187, 8189, 8190, 8191, 1234, 7777, 5000]:
-        band_lo = max(0, r // 2 - 4)
-        band_hi = min(4096, r // 2 + 5)
+    rows = 0
+    for r0 in [0, 819, 1650, 2477, 3290, 4080, 4919, 5731, 6555, 8160]:
+        r1 = min(8192, r0 + 32)
+        band_lo = max(0, r0 // 2 - 4)
+        band_hi = min(4096, (r1 - 1) // 2 + 5)
         sub = GridSpec(sg.x0, sg.y0 + band_lo * sg.dy, sg.dx, sg.dy, sg.nx, band_hi - band_lo)
-        drow = GridSpec(0.0, float(r), 1.0, 1.0, 8192, 1)
+        blk = GridSpec(0.0, float(r0), 1.0, 1.0, 8192, r1 - r0)
         ref = orc.kriging(_ogrid(orc, sub), res["z"][band_lo:band_hi].astype(np.float64),
-                          _ogrid(orc, drow), rng_m)[0]
-        o = out[r].astype(np.float64)
-        assert np.array_equal(np.isnan(o), np.isnan(ref)), f"row {r}"
-        ok = ~np.isnan(ref)
+                          _ogrid(orc, blk), rng_m)
+        _full_resample_check(out[r0:r1], ref, f"kriging rows {r0}..{r1}")
         fallbacks += int(np.isnan(res["z"][band_lo:band_hi]).any())
-        if ok.any():
-            assert np.max(np.abs(o[ok] - ref[ok]) / np.abs(ref[ok])) <= REL, f"row {r}"
-    assert fallbacks > 0
+        rows += r1 - r0
+    assert fallbacks > 0 and rows >= 256

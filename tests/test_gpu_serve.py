@@ -113,6 +113,13 @@ def test_serving_matches_oracle_on_union(ag, orc, mode):
     for v, g in enumerate(grids):
         filled += _check(orc, g, reqs, v, *out[v], label=f"mode {mode} vehicle {v}")
     assert filled > 1000
+    for v, g in enumerate(grids):
+        x, y, zz = _union(reqs, v)
+        lo, hi = orc.idw_bounds(_ogrid(orc, g), x, y, zz, 6.0, 0, bin_log2=16)
+        z = out[v][0]
+        ok = ~np.isnan(z)
+        assert np.all(z[ok] >= lo[ok].astype(np.float32))
+        assert np.all(z[ok] <= hi[ok].astype(np.float32))
     # the planted hits read out as the mean of the coincident soundings
     g, v = grids[reqs[0].vehicle], reqs[0].vehicle
     z = out[v][0]
@@ -183,25 +190,25 @@ def test_serving_admission_and_retire(ag, orc):
     s.close()
 
 
-def test_serving_full_size_sampled(ag, orc):
+def test_serving_full_size(ag, orc):
     """16 vehicles with 2048^2 grids at 2 m and cfg-size requests
     (2k..50k soundings of a +-60 deg fan at 150 m altitude), batched as
-    served: every vehicle checked on 64 sampled nodes in its swath."""
+    served: every node of every vehicle's grid against the oracle on the union
+    of its soundings -- counts and NaN masks exact (nodes left empty by either
+    side included), depths within 1e-5, every value within the depth range of
+    its soundings."""
     grids, reqs = serving_schedule(duration=0.4)
     out, infos = _run(ag, grids, reqs, ag.AUV_SERVE_BATCHED, max_request=50000)
     assert all(i.state == ag.AUV_T_DONE for i in infos)
-    rng = np.random.default_rng(17)
+    filled = empty = 0
     for v, g in enumerate(grids):
         z, c = out[v]
-        have = np.flatnonzero(c.reshape(-1) > 0)
-        if have.size == 0:
-            continue
-        nodes = np.sort(rng.choice(have, size=min(64, have.size), replace=False))
+        n = _check(orc, g, reqs, v, z, c, label=f"vehicle {v}")
         x, y, zz = _union(reqs, v)
-        oz, oc, _ = orc.idw(_ogrid(orc, g), x, y, zz, 6.0, 2.0, 1, 0, bin_log2=16, nodes=nodes)
-        gz = z.reshape(-1)[nodes].astype(np.float64)
-        assert np.array_equal(c.reshape(-1)[nodes], oc), f"vehicle {v}: counts differ"
-        ok = ~np.isnan(oz)
-        assert np.array_equal(np.isnan(gz), ~ok)
-        err = np.abs(gz[ok] - oz[ok]) / np.abs(oz[ok])
-        assert err.max() <= REL, f"vehicle {v}: max rel err {err.max():.3e}"
+        lo, hi = orc.idw_bounds(_ogrid(orc, g), x, y, zz, 6.0, 0, bin_log2=16)
+        ok = ~np.isnan(z)
+        assert np.all(z[ok] >= lo[ok].astype(np.float32)), f"vehicle {v}: below range"
+        assert np.all(z[ok] <= hi[ok].astype(np.float32)), f"vehicle {v}: above range"
+        filled += n
+        empty += int((c == 0).sum())
+    assert filled > 100000 and empty > 100000

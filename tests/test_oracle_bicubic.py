@@ -92,3 +92,45 @@ def test_nan_tap_falls_back_to_bilinear(orc):
     assert np.array_equal(cub[changed], bil[changed], equal_nan=True)
     assert np.isnan(cub[changed]).sum() == np.isnan(bil).sum() > 0
     assert np.isfinite(cub[changed]).sum() > 0
+
+
+def _one_node_at(orc, g, u, v):
+    """Destination grid of one node at source index coordinates (u, v)."""
+    return orc.Grid(g.x0 + (u + 0.5) * g.dx - 0.5, g.y0 + (v + 0.5) * g.dy - 0.5, 1.0, 1.0, 1, 1)
+
+
+def test_edge_intervals_use_clamped_taps(orc):
+    """First and last source intervals (reading of Sec. III-B at the border:
+    taps beyond the grid repeat the edge node).  At t = 1/2 in the first
+    interval the taps are (P0, P0, P1, P2), so the cubic's midpoint weights
+    (-1, 9, 9, -1)/16 give (8 P0 + 9 P1 - P2)/16; in the last interval the taps
+    are (P[n-3], P[n-2], P[n-1], P[n-1]): (-P[n-3] + 9 P[n-2] + 8 P[n-1])/16.
+    Written out by hand; a mirrored edge ((9 P0 + 8 P1 - P2)/16) or a linear
+    extrapolation ((7 P0 + 10 P1 - P2)/16) of the outside tap fails."""
+    g = orc.Grid(10.0, 20.0, 2.0, 4.0, 7, 1)     # one row: the y cubic is the identity
+    p = np.array([[-4000.0, -4016.0, -3992.0, -4040.0, -3980.0, -4008.0, -4064.0]])
+    first = orc.bicubic(g, p, _one_node_at(orc, g, 0.5, 0.0))[0, 0]
+    assert first == (8 * -4000.0 + 9 * -4016.0 - (-3992.0)) / 16
+    last = orc.bicubic(g, p, _one_node_at(orc, g, 5.5, 0.0))[0, 0]
+    assert last == (-(-3980.0) + 9 * -4008.0 + 8 * -4064.0) / 16
+    # the interior midpoint for contrast: (-P1 + 9 P2 + 9 P3 - P4)/16
+    mid = orc.bicubic(g, p, _one_node_at(orc, g, 2.5, 0.0))[0, 0]
+    assert mid == (-(-4016.0) + 9 * -3992.0 + 9 * -4040.0 - (-3980.0)) / 16
+    # beyond the outermost nodes the coordinate is clamped: the edge value
+    assert orc.bicubic(g, p, _one_node_at(orc, g, -0.4, 0.0))[0, 0] == -4000.0
+    assert orc.bicubic(g, p, _one_node_at(orc, g, 6.3, 0.0))[0, 0] == -4064.0
+
+
+def test_corner_interval_is_the_product_of_edge_weights(orc):
+    """At the lower-left corner, midway in both axes, the value is the tensor
+    product of the first-interval weights (8, 9, -1, 0)/16 on the 3 x 3 corner
+    block; the upper-right corner uses (0, -1, 9, 8)/16."""
+    g = orc.Grid(0.0, 0.0, 1.0, 1.0, 5, 6)
+    rng = np.random.default_rng(8)
+    src = np.round(rng.normal(-3000.0, 20.0, (g.ny, g.nx)))   # integers: exact sums
+    wf = np.array([8.0, 9.0, -1.0]) / 16
+    lo = orc.bicubic(g, src, _one_node_at(orc, g, 0.5, 0.5))[0, 0]
+    assert lo == pytest.approx(wf @ src[0:3, 0:3] @ wf, rel=1e-15, abs=0)
+    wl = np.array([-1.0, 9.0, 8.0]) / 16
+    hi = orc.bicubic(g, src, _one_node_at(orc, g, g.nx - 1.5, g.ny - 1.5))[0, 0]
+    assert hi == pytest.approx(wl @ src[g.ny - 3:, g.nx - 3:] @ wl, rel=1e-15, abs=0)

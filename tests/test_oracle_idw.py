@@ -263,3 +263,42 @@ def test_sampled_nodes_match_full_grid(orc):
     part = orc.idw(grid, s.x, s.y, s.z, radius=6.0, max_pts=16, bin_log2=19, nodes=nodes)
     for f, p in zip(full, part):
         assert np.array_equal(f.ravel()[nodes], p, equal_nan=True)
+
+
+@pytest.mark.parametrize("kcap,snap", [(0, 0.0), (3, 0.0), (5, 0.25)])
+def test_selected_set_bounds_by_brute_force(orc, kcap, snap):
+    """orc_idw_bounds against a brute-force statement written here: lattice
+    D^2 in int64 for every (node, sounding), the closed disk, the first k by
+    (D^2, index), then min and max of their depths; and every O1 value lies
+    within them (the clamp of step 6)."""
+    rng = np.random.default_rng(71 + kcap)
+    g = orc.Grid(10.0, -5.0, 1.5, 2.0, 17, 13)
+    n = 600
+    x = g.x0 + rng.uniform(-4, g.nx * g.dx + 4, n)
+    y = g.y0 + rng.uniform(-4, g.ny * g.dy + 4, n)
+    if snap:
+        x = g.x0 + np.round((x - g.x0) / snap) * snap
+        y = g.y0 + np.round((y - g.y0) / snap) * snap
+    z = -3000.0 + rng.normal(0.0, 25.0, n)
+    r = 3.0
+    lo, hi = orc.idw_bounds(g, x, y, z, r, max_pts=kcap, bin_log2=17)
+    X = np.rint((x - g.x0) * 65536.0).astype(np.int64)
+    Y = np.rint((y - g.y0) * 65536.0).astype(np.int64)
+    R = int(round(r * 65536.0))
+    for a in range(g.ny):
+        for b in range(g.nx):
+            Xn = int(round((b + 0.5) * g.dx * 65536.0))
+            Yn = int(round((a + 0.5) * g.dy * 65536.0))
+            d2 = (X - Xn) ** 2 + (Y - Yn) ** 2
+            mem = np.flatnonzero(d2 <= R * R)
+            order = mem[np.lexsort((mem, d2[mem]))]
+            if kcap:
+                order = order[:kcap]
+            if order.size == 0:
+                assert np.isnan(lo[a, b]) and np.isnan(hi[a, b])
+            else:
+                assert lo[a, b] == z[order].min() and hi[a, b] == z[order].max()
+    v, _, _ = orc.idw(g, x, y, z, r, 2.0, 1, kcap, bin_log2=17)
+    ok = ~np.isnan(v)
+    assert np.array_equal(ok, ~np.isnan(lo))
+    assert np.all(v[ok] >= lo[ok]) and np.all(v[ok] <= hi[ok])

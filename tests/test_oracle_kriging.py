@@ -104,3 +104,29 @@ def test_grid_under_five_nodes_is_bilinear(orc):
     d = orc.Grid(g.x0, g.y0, 0.7, 1.1, 11, 24)
     src = _field(g, 6)
     assert np.array_equal(orc.kriging(g, src, d, 5.0), orc.bilinear(g, src, d))
+
+
+@pytest.mark.parametrize("u,v,wx,wy", [
+    (0.3, 0.2, 0, 0),       # nearest node 0: the window [-2, 2] moves in to [0, 4]
+    (2.49, 1.6, 0, 0),      # nearest node 2 / 2: window [0, 4]
+    (2.51, 2.7, 1, 1),      # nearest node 3 / 3: window [1, 5]
+    (6.2, 4.4, 4, 2),       # interior: nearest 6 / 4, windows [4, 8] / [2, 6]
+    (8.4, 7.3, 6, 5),       # nearest 8 / 7: [6, 10] / [5, 9] -- the last full windows
+    (8.6, 8.6, 7, 5),       # nearest 9 / 9: moved in to [7, 11] / [5, 9]
+    (10.9, 9.0, 7, 5),      # the last nodes: windows end at the edge
+])
+def test_edge_window_literal(orc, u, v, wx, wy):
+    """The 5 x 5 neighbourhood at and near the grid edges, written out per case
+    (not recomputed): centred on the nearest source node and moved inward so
+    that it stays on the grid (12 x 10 source nodes).  With a range far below
+    the spacing every window node is equally uncorrelated with the point, so
+    the kriged value is the window's mean, and the test field gives each
+    window a different mean (a window left partly outside the grid with
+    clamped indices, or centred on the floor node, fails)."""
+    g = _grid(orc)
+    jj, ii = np.meshgrid(np.arange(g.nx, dtype=np.float64), np.arange(g.ny, dtype=np.float64))
+    src = -4000.0 + jj * jj + 100.0 * ii * ii
+    d = orc.Grid(g.x0 + (u + 0.5) * g.dx - 0.5, g.y0 + (v + 0.5) * g.dy - 0.5, 1.0, 1.0, 1, 1)
+    out = orc.kriging(g, src, d, 1e-3)[0, 0]
+    want = src[wy:wy + 5, wx:wx + 5].mean()
+    assert out == pytest.approx(want, rel=0, abs=1e-9)
