@@ -373,7 +373,10 @@ auv_status auv_session_drain(auv_session *s);
 /* Wait for the vehicle's submitted requests, then enqueue the read-out of its
  * grid on `stream`: z_out device float [ny][nx] (NaN: no value; clamped to
  * the depth range of the node's soundings like auv_interp_idw), cnt_out
- * device int32 [ny][nx] (nullable; soundings within the radius so far). */
+ * device int32 [ny][nx] (nullable; soundings within the radius so far).
+ * The read-out covers exactly the requests submitted before the call: the
+ * session's later launches wait for it on the device (an event recorded on
+ * `stream`), so a submit right after it cannot change what it reads. */
 auv_status auv_session_read_grid(auv_session *s, int32_t vehicle, float *z_out,
                                  int32_t *cnt_out, auv_stream stream);
 

@@ -19,7 +19,7 @@
 // processing time first on an estimated cost, so each XCD's L2 mostly sees
 // the bins of a few items.
 #include "idw_dense_impl.hpp"
-#include "idw_window_impl.hpp"
+#include "idw_span_impl.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -46,6 +46,7 @@ struct IdwItem {
     WinGeom g;
     int32_t ntx, ntiles;
     int32_t dense, pmode;
+    int32_t span;  // sparse items: the span form covers it (else the window form)
 };
 
 __global__ void k_reset_queues(int32_t *qhead)
@@ -83,16 +84,24 @@ __global__ __launch_bounds__(64) void k_idw_batch_window(const IdwItem *__restri
                                                          const int32_t *__restrict__ qgrab,
                                                          int32_t *__restrict__ qhead)
 {
-    __shared__ float2 s_nd[win::kAcc];
-    __shared__ int s_cnt[win::kAcc];
-    __shared__ float2 s_mm[win::kAcc];
-    __shared__ unsigned long long s_key[win::kAcc];
-    __shared__ float s_emax[win::kAcc];
-    __shared__ int s_beg[win::kMaxRows];
-    __shared__ int s_off[win::kMaxRows + 1];
-    __shared__ int4 s_rec[128];
-    const win::WinSmem sm{s_nd, s_cnt, s_mm, s_key, nullptr, nullptr, nullptr, s_emax, s_beg,
-                          s_off, s_rec, s_rec + 1, nullptr};
+    // one tile at a time: the span form's LDS and the window form's share
+    // the same bytes
+    struct WinLds {
+        float2 nd[win::kAcc];
+        int cnt[win::kAcc];
+        float2 mm[win::kAcc];
+        unsigned long long key[win::kAcc];
+        float emax[win::kAcc];
+        int beg[win::kMaxRows];
+        int off[win::kMaxRows + 1];
+        int4 rec[128];
+    };
+    __shared__ union {
+        span::Smem<win::kTW, win::kTH> sp;
+        WinLds w;
+    } lds;
+    const win::WinSmem sm{lds.w.nd, lds.w.cnt, lds.w.mm, lds.w.key, nullptr, nullptr, nullptr,
+                          lds.w.emax, lds.w.beg, lds.w.off, lds.w.rec, lds.w.rec + 1, nullptr};
     const int home = blockIdx.x & (kQueues - 1);
     for (int k = 0; k < kQueues; ++k) {
         const int q = (home + k) & (kQueues - 1);
@@ -106,11 +115,17 @@ __global__ __launch_bounds__(64) void k_idw_batch_window(const IdwItem *__restri
                                          __builtin_amdgcn_readfirstlane(wv.y));
                 const IdwItem &it = items[w.x];
                 // integer powers share one variant (the power is a runtime
-                // value there); a general power needs the rescaling variant
-                if (it.pmode != 0)
+                // value there); a general power needs the window form's
+                // rescaling variant
+                if (it.span) {
+                    __syncthreads();  // the previous tile is finished with the LDS
+                    span::span_tile<3, -1, win::kTW, win::kTH>(it.bv, it.a, it.g, w.y, it.ntx,
+                                                               lds.sp);
+                } else if (it.pmode != 0) {
                     run_window<-1, 1>(it, w.y, sm);
-                else
+                } else {
                     run_window<0, 1>(it, w.y, sm);
+                }
             }
         }
     }
@@ -373,6 +388,7 @@ auv_status build_tables(auv_batch *b, char *ws)
         d.a = a;
         d.pmode = pmode_of(it.params.power);
         d.dense = b->algo[i] == AUV_ALGO_DENSE;
+        d.span = 0;
         bool ok = true;
         if (d.dense) {
             ok = it.params.max_pts >= 1 && it.params.max_pts <= kBatchDenseK;
@@ -383,6 +399,7 @@ auv_status build_tables(auv_batch *b, char *ws)
             const unsigned __int128 top = (unsigned __int128)((unsigned long long)a.R * a.R)
                                           << bv.idx_bits;
             ok = ok && top < ((unsigned __int128)1 << 64);
+            d.span = ok && span::span_ok(bv, a, d.g, d.pmode) ? 1 : 0;
             d.ntx = (it.grid.nx + win::kTW - 1) / win::kTW;
             d.ntiles = d.ntx * ((it.grid.ny + win::kTH - 1) / win::kTH);
         }

@@ -1,7 +1,7 @@
 // Window-form IDW: launchers of the exact lattice path, the window geometry
 // and the dispatch to the precision variants (idw_window_prec.hip).  The
 // kernel itself is in idw_window_impl.hpp.
-#include "idw_window_impl.hpp"
+#include "idw_span_impl.hpp"
 
 #include <cmath>
 
@@ -42,6 +42,15 @@ auv_status launch_idw_window(const auv_bin_view &bv, const IdwArgs &a, const Win
     const int ntx = (a.nx + kTW - 1) / kTW, nty = (a.ny + kTH - 1) / kTH;
     if (a.precision != AUV_P_FP32_REBASE)
         return launch_idw_window_prec(bv, a, g, pmode, st);
+    if (span::span_ok(bv, a, g, pmode)) {
+        switch (a.mode) {
+        case 1: span::launch_shape<1, 16, 16>(bv, a, g, pmode, st); break;
+        case 2: span::launch_shape<2, 16, 16>(bv, a, g, pmode, st); break;
+        default: span::launch_shape<3, 16, 16>(bv, a, g, pmode, st); break;
+        }
+        AUV_HIP(hipGetLastError());
+        return AUV_OK;
+    }
     switch (a.mode) {
     case 1: launch_mode<1, AUV_P_FP32_REBASE>(bv, a, g, ntx, nty, pmode, st); break;
     case 2: launch_mode<2, AUV_P_FP32_REBASE>(bv, a, g, ntx, nty, pmode, st); break;

@@ -2,8 +2,10 @@
 //
 // One launch (one request in FIFO mode, up to max_batch requests of distinct
 // vehicles in batched mode) enqueues on the session stream:
-//   H2D copies of the launch table and of each request's slot (bounding-box
-//   seed + x, y, z)
+//   k_serve_stage       reads the launch table and each request's slot
+//                       (bounding-box seed + x, y, z) from pinned host memory
+//                       and writes them to the device (no runtime copy: the
+//                       copy path of the runtime stalled now and then)
 //   batched row binning (the kernels behind auv_bin_points); its histogram
 //                       kernel also widens each request's lattice bounding
 //                       box over the binned soundings
@@ -170,6 +172,45 @@ __global__ __launch_bounds__(64 * kServeParts) void k_serve_update(
     }
 }
 
+// Host-to-device staging of one launch: job j copies bytes [0, n) from
+// pinned, coherent host memory (device-visible) to device memory, 16 bytes
+// per lane.  Sizes and addresses are multiples of 16.
+constexpr int kStageJobs = kMaxBatchReq + 1;
+constexpr int kStageThreads = 256;
+constexpr int kStageChunk = kStageThreads * 16 * 4;  // bytes per block
+
+struct StageJob {
+    const int4 *src;
+    int4 *dst;
+    int64_t n16;  // 16-byte words
+};
+struct StageArgs {
+    int32_t count;
+    StageJob job[kStageJobs];
+};
+
+__global__ __launch_bounds__(kStageThreads) void k_serve_stage(StageArgs args)
+{
+    const int j = blockIdx.y;
+    if (j >= args.count)
+        return;
+    const StageJob jb = args.job[j];
+    const int64_t base = (int64_t)blockIdx.x * (kStageChunk / 16);
+    int4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t i = base + u * kStageThreads + threadIdx.x;
+        if (i < jb.n16)
+            v[u] = jb.src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t i = base + u * kStageThreads + threadIdx.x;
+        if (i < jb.n16)
+            jb.dst[i] = v[u];
+    }
+}
+
 // Read-out: z = z_ref + num / den, clamped to the depth range of the node's
 // soundings; NaN where no sounding, or fewer than min_pts and no hit (a hit's
 // weight makes den >= 2^80).
@@ -313,9 +354,10 @@ struct auv_session {
     size_t arena_bytes = 0;
     auv::Arena alloc;
     size_t slot_stage_bytes = 0, slot_ws_bytes = 0, per_vehicle = 0;
-    std::vector<char *> slot_host, slot_dev, slot_ws;
+    std::vector<char *> slot_host, slot_map, slot_dev, slot_ws;  // slot_map: device view of slot_host
     std::vector<int32_t> free_slots;
-    std::vector<char *> table_host, table_dev;
+    std::vector<char *> table_host, table_map, table_dev;  // table_map: device view of table_host
+    hipEvent_t read_ev = nullptr;  // orders a read-out before the next launch
     std::vector<int> free_tables;
     std::vector<hipEvent_t> free_events, all_events;
     hipStream_t stream = nullptr;
@@ -500,10 +542,21 @@ auv_status enqueue_launch(auv_session *s, const std::vector<Pick> &picks, int ta
     int32_t *d_offs = reinterpret_cast<int32_t *>(td + L.offs);
     int32_t *d_counters = reinterpret_cast<int32_t *>(td + L.counters);
     hipStream_t st = s->stream;
-    AUV_HIP(hipMemcpyAsync(td, th, L.bytes, hipMemcpyHostToDevice, st));
-    for (const Pick &p : picks)
-        AUV_HIP(hipMemcpyAsync(s->slot_dev[p.slot], s->slot_host[p.slot],
-                               kSlotHeader + 24 * (size_t)p.n, hipMemcpyHostToDevice, st));
+    // the table and the requests reach the device through one staging kernel
+    StageArgs sa;
+    sa.count = 1 + B;
+    sa.job[0] = StageJob{reinterpret_cast<const int4 *>(s->table_map[table]),
+                         reinterpret_cast<int4 *>(td), (int64_t)(L.bytes / 16)};
+    int64_t most = sa.job[0].n16;
+    for (int i = 0; i < B; ++i) {
+        const Pick &p = picks[i];
+        const int64_t n16 = (int64_t)((kSlotHeader + 24 * (size_t)p.n + 15) / 16);
+        sa.job[1 + i] = StageJob{reinterpret_cast<const int4 *>(s->slot_map[p.slot]),
+                                 reinterpret_cast<int4 *>(s->slot_dev[p.slot]), n16};
+        most = std::max(most, n16);
+    }
+    const dim3 sgrid((unsigned)((most * 16 + kStageChunk - 1) / kStageChunk), (unsigned)sa.count);
+    k_serve_stage<<<sgrid, kStageThreads, 0, st>>>(sa);
     AUV_TRY_S(launch_binning_batch(d_rows, d_offs, d_offs + (B + 1), d_offs + 2 * (B + 1), B,
                                    hist_off[B], scat_off[B], sort_off[B], max_nbx, max_nby,
                                    st));
@@ -694,13 +747,18 @@ auv_status auv_session_create(const auv_session_desc *desc, void *arena, size_t 
     AUV_HIP(hipGetDevice(&s->device));
     (void)hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device);
     AUV_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+    AUV_HIP(hipEventCreateWithFlags(&s->read_ev, hipEventDisableTiming));
     // carve: tables, then slots; the rest is for vehicles
     const TableLayout L = table_layout();
     size_t off = 0;
     for (int t = 0; t < 2; ++t) {
-        char *h = nullptr;
-        AUV_HIP(hipHostMalloc(reinterpret_cast<void **>(&h), L.bytes, hipHostMallocDefault));
+        char *h = nullptr, *m = nullptr;
+        // coherent: the staging kernel reads what the host wrote just before
+        AUV_HIP(hipHostMalloc(reinterpret_cast<void **>(&h), L.bytes,
+                              hipHostMallocMapped | hipHostMallocCoherent));
         s->table_host.push_back(h);
+        AUV_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&m), h, 0));
+        s->table_map.push_back(m);
         s->table_dev.push_back(s->arena + off);
         off += align256(L.bytes);
         s->free_tables.push_back(t);
@@ -710,9 +768,12 @@ auv_status auv_session_create(const auv_session_desc *desc, void *arena, size_t 
         s->free_events.push_back(ev);
     }
     for (int i = 0; i < desc->slots; ++i) {
-        char *h = nullptr;
-        AUV_HIP(hipHostMalloc(reinterpret_cast<void **>(&h), stage, hipHostMallocDefault));
+        char *h = nullptr, *m = nullptr;
+        AUV_HIP(hipHostMalloc(reinterpret_cast<void **>(&h), stage,
+                              hipHostMallocMapped | hipHostMallocCoherent));
         s->slot_host.push_back(h);
+        AUV_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&m), h, 0));
+        s->slot_map.push_back(m);
         s->slot_dev.push_back(s->arena + off);
         off += stage;
         s->slot_ws.push_back(s->arena + off);
@@ -848,6 +909,9 @@ auv_status auv_session_read_grid(auv_session *s, int32_t vehicle, float *z_out, 
         acc, acc + plane, reinterpret_cast<const int32_t *>(acc + 2 * plane), acc + 3 * plane,
         acc + 4 * plane, V.nodes, V.zref, s->desc.params.min_pts, z_out, cnt_out);
     AUV_HIP(hipGetLastError());
+    // later launches (picked after this point, the lock held) wait for the read
+    AUV_HIP(hipEventRecord(s->read_ev, st));
+    AUV_HIP(hipStreamWaitEvent(s->stream, s->read_ev, 0));
     return AUV_OK;
 }
 
@@ -886,6 +950,8 @@ void auv_session_destroy(auv_session *s)
         (void)hipStreamSynchronize(s->stream);
     for (hipEvent_t e : s->all_events)
         (void)hipEventDestroy(e);
+    if (s->read_ev)
+        (void)hipEventDestroy(s->read_ev);
     for (char *h : s->slot_host)
         (void)hipHostFree(h);
     for (char *h : s->table_host)
