@@ -92,8 +92,12 @@ enum {
                             least max_pts / 2 (and 1 <= max_pts <= 32): many
                             nodes would exceed the cap; else sparse */
     AUV_ALGO_SPARSE = 1, /* node windows scattered from each sounding */
-    AUV_ALGO_DENSE = 2   /* per-node ring search with a register top-k list;
+    AUV_ALGO_DENSE = 2,  /* per-node ring search with a register top-k list;
                             needs 1 <= max_pts <= 32 and AUV_P_FP32_REBASE */
+    AUV_ALGO_SPAN = 3    /* sparse, span form: (sounding, node) pairs packed 64
+                            per instruction, LDS atomics; integer powers
+                            1..3 with AUV_P_FP32_REBASE, else the window
+                            form runs */
 };
 
 /* Library version string (static storage). */

@@ -31,6 +31,7 @@ AUV_P_FP32_ABSOLUTE = 2
 AUV_ALGO_AUTO = 0
 AUV_ALGO_SPARSE = 1
 AUV_ALGO_DENSE = 2
+AUV_ALGO_SPAN = 3
 
 
 class AuvError(RuntimeError):

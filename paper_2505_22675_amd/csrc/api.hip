@@ -262,7 +262,7 @@ auv_status auv_interp_idw(const auv_grid *grid, const auv_bins *bins,
         return fail(AUV_ERR_INVALID, "power must be in (0, 64]");
     if (params->min_pts < 0 || params->max_pts < 0)
         return fail(AUV_ERR_INVALID, "min_pts/max_pts must be >= 0");
-    if (params->algo < AUV_ALGO_AUTO || params->algo > AUV_ALGO_DENSE)
+    if (params->algo < AUV_ALGO_AUTO || params->algo > AUV_ALGO_SPAN)
         return fail(AUV_ERR_INVALID, "unknown algo");
     if (params->precision < AUV_P_FP32_REBASE || params->precision > AUV_P_FP32_ABSOLUTE)
         return fail(AUV_ERR_INVALID, "unknown precision variant");
@@ -298,6 +298,7 @@ auv_status auv_interp_idw(const auv_grid *grid, const auv_bins *bins,
                         "the dense form needs 1 <= max_pts <= 32 and AUV_P_FP32_REBASE");
         a.dense = params->algo == AUV_ALGO_DENSE ||
                   (params->algo == AUV_ALGO_AUTO && dense_ok && lambda >= 0.5 * params->max_pts);
+        a.span = params->algo == AUV_ALGO_SPAN;
     }
     a.z_out = z_out;
     a.cnt_out = cnt_out;

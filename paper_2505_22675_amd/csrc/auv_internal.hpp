@@ -192,6 +192,7 @@ struct IdwArgs {
     float r2f;                // radius^2 in m^2, FP32 (precision variants)
     double x0, y0;            // grid origin (precision variants)
     bool dense;               // use the dense (ring search, top-k) form
+    bool span;                // sparse: the span form where it applies
     int32_t pmode;            // 1, 2, 3: integer power (fast weights), 0: general
     float *z_out;
     int32_t *cnt_out;

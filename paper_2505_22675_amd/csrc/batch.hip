@@ -274,7 +274,7 @@ auv_status validate_item(const auv_batch_item &it, int i)
         return fail(AUV_ERR_INVALID, tag + "bad power / min_pts / max_pts");
     if (p.precision != AUV_P_FP32_REBASE)
         return fail(AUV_ERR_INVALID, tag + "batches run the exact FP64-rebase form only");
-    if (p.algo < AUV_ALGO_AUTO || p.algo > AUV_ALGO_DENSE)
+    if (p.algo < AUV_ALGO_AUTO || p.algo > AUV_ALGO_SPAN)
         return fail(AUV_ERR_INVALID, tag + "unknown algo");
     return AUV_OK;
 }
@@ -325,6 +325,7 @@ void item_views(const auv_batch *b, int i, char *ws, const BinGeom &geom, int32_
     x.nn_idx_out = it.nn_idx_out;
     x.nn_z_out = it.nn_z_out;
     x.dense = algo == AUV_ALGO_DENSE;
+    x.span = algo == AUV_ALGO_SPAN;
     x.pmode = pmode_of(it.params.power);
     *a = x;
 }
@@ -399,7 +400,7 @@ auv_status build_tables(auv_batch *b, char *ws)
             const unsigned __int128 top = (unsigned __int128)((unsigned long long)a.R * a.R)
                                           << bv.idx_bits;
             ok = ok && top < ((unsigned __int128)1 << 64);
-            d.span = ok && span::span_ok(bv, a, d.g, d.pmode) ? 1 : 0;
+            d.span = ok && a.span && span::span_ok(bv, a, d.g, d.pmode) ? 1 : 0;
             d.ntx = (it.grid.nx + win::kTW - 1) / win::kTW;
             d.ntiles = d.ntx * ((it.grid.ny + win::kTH - 1) / win::kTH);
         }

@@ -42,7 +42,7 @@ auv_status launch_idw_window(const auv_bin_view &bv, const IdwArgs &a, const Win
     const int ntx = (a.nx + kTW - 1) / kTW, nty = (a.ny + kTH - 1) / kTH;
     if (a.precision != AUV_P_FP32_REBASE)
         return launch_idw_window_prec(bv, a, g, pmode, st);
-    if (span::span_ok(bv, a, g, pmode)) {
+    if (a.span && span::span_ok(bv, a, g, pmode)) {
         switch (a.mode) {
         case 1: span::launch_shape<1, 16, 16>(bv, a, g, pmode, st); break;
         case 2: span::launch_shape<2, 16, 16>(bv, a, g, pmode, st); break;

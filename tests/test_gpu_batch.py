@@ -118,6 +118,8 @@ def _mixed_items(ag):
     d = tiles[int(np.argmax([len(t.x) for t in tiles]))]
     items.append(_Item(ag, d, max_pts=24, algo=ag.AUV_ALGO_DENSE))  # dense, k > 16
     items.append(_Item(ag, tiles[0], with_nearest=False, with_counts=False))
+    items.append(_Item(ag, tiles[1], algo=ag.AUV_ALGO_SPAN))          # span form
+    items.append(_Item(ag, f, power=3.0, max_pts=0, algo=ag.AUV_ALGO_SPAN))
     return items
 
 

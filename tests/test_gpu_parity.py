@@ -48,14 +48,15 @@ def _assert_idw_equal(gz, gc, gn, gnz, oz, oc, on, z_src, label=""):
     return err
 
 
-def _run_idw(ag, s, bin_log2=0, max_pts=None, min_pts=None, power=None, radius=None):
+def _run_idw(ag, s, bin_log2=0, max_pts=None, min_pts=None, power=None, radius=None,
+             algo=0):
     grid = ag.auv_grid_create(s.grid)
     bins = ag.auv_bin_points(grid, _dev(s.x), _dev(s.y), _dev(s.z),
                              s.radius if radius is None else radius, bin_log2)
     out = ag.grid_idw(grid, bins, power=s.power if power is None else power,
                       min_pts=s.min_pts if min_pts is None else min_pts,
                       max_pts=s.max_pts if max_pts is None else max_pts,
-                      with_counts=True, with_nearest=True)
+                      with_counts=True, with_nearest=True, algo=algo)
     torch.cuda.synchronize()
     return {k: v.cpu().numpy() for k, v in out.items()}, grid, bins
 
@@ -232,6 +233,53 @@ def test_cfg2_full_grid_parity(ag, orc, cfg2_run):
     lo, hi = orc.idw_bounds(og, s.x, s.y, s.z, s.radius, s.max_pts, bin_log2=19)
     assert _assert_within_bounds(res["z"], lo, hi, "cfg2") > 0.75 * oz.size
     assert np.all(res["cnt"] <= 16)
+
+
+def test_idw_span_form_parity(ag, orc, cfg2_run):
+    """The span form (AUV_ALGO_SPAN) against the oracle: cfg1 (no cap, about 25
+    members per node), swaths with caps that bind and integer powers 1..3,
+    lattice-snapped ties and hits on a ragged grid, and every node of cfg2."""
+    from gen import GridSpec
+    span = ag.AUV_ALGO_SPAN
+    s = workload_cfg1()
+    res, _, _ = _run_idw(ag, s, algo=span)
+    oz, oc, on = orc.idw(_ogrid(orc, s.grid), s.x, s.y, s.z, s.radius, s.power, s.min_pts,
+                         s.max_pts, bin_log2=20)
+    _assert_idw_equal(res["z"], res["cnt"], res["nn_idx"], res["nn_z"], oz, oc, on, s.z,
+                      "span cfg1")
+    s = small_swath(nodes=300, pings=140, beams=120, n_lines=4, seed=53, x0=5000.0, y0=-700.0)
+    for kcap, power in ((16, 2.0), (3, 1.0), (0, 3.0)):
+        res, _, _ = _run_idw(ag, s, max_pts=kcap, power=power, algo=span)
+        oz, oc, on = orc.idw(_ogrid(orc, s.grid), s.x, s.y, s.z, s.radius, power, 1, kcap,
+                             bin_log2=19)
+        _assert_idw_equal(res["z"], res["cnt"], res["nn_idx"], res["nn_z"], oz, oc, on, s.z,
+                          f"span swath k={kcap} p={power}")
+    rng = np.random.default_rng(54)
+    g = GridSpec(-3.0, 5.0, 0.5, 0.5, 61, 45)
+    n = 3000
+    x = g.x0 + np.round(rng.uniform(-2, 33, n) * 4) / 4
+    y = g.y0 + np.round(rng.uniform(-2, 25, n) * 4) / 4
+    z = -np.round(rng.uniform(50, 80, n), 2)
+    x[:300] = g.x0 + (rng.integers(0, 61, 300) + 0.5) * 0.5
+    y[:300] = g.y0 + (rng.integers(0, 45, 300) + 0.5) * 0.5
+    for kcap, r in ((4, 1.0), (0, 1.25)):
+        res, _, _ = _run_idw(ag, _with(g, x, y, z, r), max_pts=kcap, min_pts=2, power=2.0,
+                             algo=span)
+        oz, oc, on = orc.idw(_ogrid(orc, g), x, y, z, r, 2.0, 2, kcap, bin_log2=-1)
+        _assert_idw_equal(res["z"], res["cnt"], res["nn_idx"], res["nn_z"], oz, oc, on, z,
+                          f"span ties k={kcap} r={r}")
+    s, _, grid, bins = cfg2_run
+    out = ag.grid_idw(grid, bins, power=s.power, min_pts=s.min_pts, max_pts=s.max_pts,
+                      with_counts=True, with_nearest=True, algo=span)
+    torch.cuda.synchronize()
+    og = _ogrid(orc, s.grid)
+    oz, oc, on = orc.idw(og, s.x, s.y, s.z, s.radius, s.power, s.min_pts, s.max_pts,
+                         bin_log2=19)
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    _assert_idw_equal(res["z"], res["cnt"], res["nn_idx"], res["nn_z"], oz, oc, on, s.z,
+                      "span cfg2 full grid")
+    lo, hi = orc.idw_bounds(og, s.x, s.y, s.z, s.radius, s.max_pts, bin_log2=19)
+    _assert_within_bounds(res["z"], lo, hi, "span cfg2")
 
 
 def test_cfg4_exact_path_full_size(ag, orc):
