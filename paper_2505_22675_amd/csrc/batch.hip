@@ -89,7 +89,8 @@ __global__ __launch_bounds__(64) void k_idw_batch_window(const IdwItem *__restri
     struct WinLds {
         float2 nd[win::kAcc];
         int cnt[win::kAcc];
-        float2 mm[win::kAcc];
+        float lo[win::kAcc];
+        float hi[win::kAcc];
         unsigned long long key[win::kAcc];
         float emax[win::kAcc];
         int beg[win::kMaxRows];
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(64) void k_idw_batch_window(const IdwItem *__restri
         span::Smem<win::kTW, win::kTH> sp;
         WinLds w;
     } lds;
-    const win::WinSmem sm{lds.w.nd, lds.w.cnt, lds.w.mm, lds.w.key, nullptr, nullptr, nullptr,
+    const win::WinSmem sm{lds.w.nd, lds.w.cnt, lds.w.lo, lds.w.hi, lds.w.key, nullptr, nullptr, nullptr,
                           lds.w.emax, lds.w.beg, lds.w.off, lds.w.rec, lds.w.rec + 1, nullptr};
     const int home = blockIdx.x & (kQueues - 1);
     for (int k = 0; k < kQueues; ++k) {

@@ -112,6 +112,25 @@ __device__ inline int wave_sum_i(int v)
 
 __device__ inline int wave_count(bool p) { return __popcll(__ballot(p)); }
 
+// Non-returning LDS atomics (workgroup scope, relaxed): ds_add_u32,
+// ds_min_u64, ds_min_f32, ds_max_f32.  Used where lanes of one instruction
+// update distinct words, so nothing serialises.
+template <class T>
+__device__ inline void lds_add(T *p, T v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <class T>
+__device__ inline void lds_min(T *p, T v)
+{
+    __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <class T>
+__device__ inline void lds_max(T *p, T v)
+{
+    __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Best key (D^2, index) and its depth, reduced over the wave.
 __device__ inline void wave_best(double &d2, int &idx, float &z)
 {
@@ -461,7 +480,7 @@ constexpr int kAcc = kTH * kRS;
 struct WinSmem {
     float2 *nd;                 // numerator, denominator        [kAcc]
     int *cnt;                   // members                       [kAcc]
-    float2 *mm;                 // smallest, largest member depth [kAcc]
+    float *lo, *hi;             // smallest, largest member depth [kAcc] each
     unsigned long long *key;    // packed (D^2 << b) | index     [kAcc] (packed)
     double *bd2;                // best D^2                      [kAcc] (unpacked)
     int *bidx;                  // best index                    [kAcc] (unpacked)
@@ -495,7 +514,8 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
     // per lane).
     float2 *const s_nd = sm.nd;
     int *const s_cnt = sm.cnt;
-    float2 *const s_mm = sm.mm;
+    float *const s_lo = sm.lo;
+    float *const s_hi = sm.hi;
     unsigned long long *const s_key = sm.key;
     double *const s_bd2 = sm.bd2;
     int *const s_bidx = sm.bidx;
@@ -540,7 +560,8 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
     for (int q = lane; q < kAcc; q += 64) {
         s_nd[q] = make_float2(0.0f, 0.0f);
         s_cnt[q] = 0;
-        s_mm[q] = make_float2(INFINITY, -INFINITY);
+        s_lo[q] = INFINITY;
+        s_hi[q] = -INFINITY;
         if constexpr (kPacked) {
             if constexpr (kKey)
                 s_key[q] = ~0ull;
@@ -720,19 +741,12 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                     if (mem) {
                         const int q = qb + qo[t];
                         const int q8 = qb8 + qo[t] * 8;
-                        int *const pc =
-                            reinterpret_cast<int *>(reinterpret_cast<char *>(s_cnt) + qb4 + qo[t] * 4);
+                        const int q4 = qb4 + qo[t] * 4;
+                        int *const pc = reinterpret_cast<int *>(reinterpret_cast<char *>(s_cnt) + q4);
+                        float *const pl = reinterpret_cast<float *>(reinterpret_cast<char *>(s_lo) + q4);
+                        float *const ph = reinterpret_cast<float *>(reinterpret_cast<char *>(s_hi) + q4);
                         float2 *const pn =
                             reinterpret_cast<float2 *>(reinterpret_cast<char *>(s_nd) + q8);
-                        float2 *const pm =
-                            reinterpret_cast<float2 *>(reinterpret_cast<char *>(s_mm) + q8);
-                        // every read of the node before any write: one LDS round trip
-                        const int cq = *pc;
-                        float2 mq = *pm;
-                        unsigned long long kq = 0ull;
-                        if constexpr (kKey)
-                            kq = *reinterpret_cast<unsigned long long *>(
-                                reinterpret_cast<char *>(s_key) + q8);
                         float2 nd = make_float2(0.0f, 0.0f);
                         float em = 0.0f;
                         if constexpr (kIdw) {
@@ -748,12 +762,16 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                             else
                                 w = D2 == 0 ? 1e30f : log_weight(d2f * a.inv_r2, a.power);
                         }
+                        // count, nearest key and depth range: non-returning LDS
+                        // atomics (no read back; lanes of one instruction hit
+                        // distinct nodes, and a wave's LDS operations execute
+                        // in program order, so the result is deterministic)
                         if constexpr (kKey) {
                             const unsigned long long key =
                                 ((unsigned long long)D2 << kb) | (unsigned)sidx;
-                            if (key < kq)
-                                *reinterpret_cast<unsigned long long *>(
-                                    reinterpret_cast<char *>(s_key) + q8) = key;
+                            lds_min(reinterpret_cast<unsigned long long *>(
+                                        reinterpret_cast<char *>(s_key) + q8),
+                                    key);
                         } else if constexpr (!kPacked) {
                             const double d2 = (double)D2, bd = s_bd2[q];
                             if (d2 < bd || (d2 == bd && sidx < s_bidx[q])) {
@@ -762,10 +780,9 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                                 s_bz[q] = spz;
                             }
                         }
-                        *pc = cq + 1;
-                        mq.x = fminf(mq.x, spz);
-                        mq.y = fmaxf(mq.y, spz);
-                        *pm = mq;
+                        lds_add(pc, 1);
+                        lds_min(pl, spz);
+                        lds_max(ph, spz);
                         if constexpr (kIdw) {
                             if constexpr (kPmode != 0) {
                                 nd.x += w * sdz;
@@ -829,13 +846,13 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                 const int64_t o = (int64_t)(ta0 + la) * a.nx + tb0 + lb;
                 const float2 nd = s_nd[q];
                 const double shift = (double)zref - a.zref_acc;
-                const float2 mm = s_mm[q];
+                const float lo = s_lo[q], hi = s_hi[q];
                 const int c0 = a.acc_cnt[o];
                 a.acc_num[o] += (float)((double)nd.x + (double)nd.y * shift);
                 a.acc_den[o] += nd.y;
                 a.acc_cnt[o] = c0 + cnt;
-                a.acc_lo[o] = c0 > 0 ? fminf(a.acc_lo[o], mm.x) : mm.x;
-                a.acc_hi[o] = c0 > 0 ? fmaxf(a.acc_hi[o], mm.y) : mm.y;
+                a.acc_lo[o] = c0 > 0 ? fminf(a.acc_lo[o], lo) : lo;
+                a.acc_hi[o] = c0 > 0 ? fmaxf(a.acc_hi[o], hi) : hi;
             }
         } else {
             const bool over = act && kcap > 0 && cnt > kcap;
@@ -860,12 +877,11 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                     // ratio is the mean of the hits, and it beats min_pts
                     const bool hole = cnt == 0 || (cnt < a.min_pts && !hit);
                     const float2 nd = s_nd[q];
-                    const float2 mm = s_mm[q];
                     // the quotient and the return to absolute depth in FP64,
                     // clamped to the members' depths, rounded once to FP32
                     const double v = (double)zref + (double)nd.x / (double)nd.y;
                     a.z_out[o] = hole ? NAN
-                                      : (float)fmin(fmax(v, (double)mm.x), (double)mm.y);
+                                      : (float)fmin(fmax(v, (double)s_lo[q]), (double)s_hi[q]);
                 }
             }
             unsigned long long om = __ballot(over);
@@ -887,7 +903,8 @@ __global__ __launch_bounds__(64) void k_idw_window(auv_bin_view bv, IdwArgs a, W
 {
     __shared__ float2 s_nd[kAcc];
     __shared__ int s_cnt[kAcc];
-    __shared__ float2 s_mm[kAcc];
+    __shared__ float s_lo[kAcc];
+    __shared__ float s_hi[kAcc];
     __shared__ unsigned long long s_key[kPacked ? kAcc : 1];
     __shared__ double s_bd2[kPacked ? 1 : kAcc];
     __shared__ int s_bidx[kPacked ? 1 : kAcc];
@@ -897,7 +914,7 @@ __global__ __launch_bounds__(64) void k_idw_window(auv_bin_view bv, IdwArgs a, W
     __shared__ int s_off[kMaxRows + 1];
     __shared__ int4 s_rec[128];
     __shared__ float4 s_rv[kPrec == AUV_P_FP32_REBASE && kPacked ? 1 : 64];
-    const WinSmem sm{s_nd, s_cnt, s_mm, s_key, s_bd2, s_bidx, s_bz, s_emax, s_beg, s_off,
+    const WinSmem sm{s_nd, s_cnt, s_lo, s_hi, s_key, s_bd2, s_bidx, s_bz, s_emax, s_beg, s_off,
                      s_rec, s_rec + 1, s_rv};
     window_tile<kMode, kPmode, kPacked, kChunks, kPrec>(
         bv, a, g, xcd_tile(blockIdx.x, ntx * nty), ntx, sm);

@@ -75,7 +75,8 @@ __global__ __launch_bounds__(64 * kServeParts) void k_serve_update(
 {
     __shared__ float2 s_nd[kServeParts][win::kAcc];
     __shared__ int s_cnt[kServeParts][win::kAcc];
-    __shared__ float2 s_mm[kServeParts][win::kAcc];
+    __shared__ float s_lo[kServeParts][win::kAcc];
+    __shared__ float s_hi[kServeParts][win::kAcc];
     __shared__ float s_emax[1];
     __shared__ int s_beg[kServeParts][win::kMaxRows];
     __shared__ int s_off[kServeParts][win::kMaxRows + 1];
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(64 * kServeParts) void k_serve_update(
     __shared__ float s_zref[kServeParts];
     __shared__ int s_task;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const win::WinSmem sm{s_nd[wave], s_cnt[wave], s_mm[wave], nullptr, nullptr, nullptr,
+    const win::WinSmem sm{s_nd[wave], s_cnt[wave], s_lo[wave], s_hi[wave], nullptr, nullptr, nullptr,
                           nullptr, s_emax, s_beg[wave], s_off[wave], s_rec[wave],
                           s_rec[wave] + 1, nullptr};
     int t0x = 0, t0y = 0, tcols = 1, nt = 0;
@@ -149,12 +150,11 @@ __global__ __launch_bounds__(64 * kServeParts) void k_serve_update(
                 const int cw = s_cnt[w][q];
                 if (cw > 0) {
                     const float2 nd = s_nd[w][q];
-                    const float2 mm = s_mm[w][q];
                     num += (double)nd.x + (double)nd.y * ((double)s_zref[w] - it.a.zref_acc);
                     den += nd.y;
                     cnt += cw;
-                    lo = fminf(lo, mm.x);
-                    hi = fmaxf(hi, mm.y);
+                    lo = fminf(lo, s_lo[w][q]);
+                    hi = fmaxf(hi, s_hi[w][q]);
                 }
             }
             if (cnt > 0) {
