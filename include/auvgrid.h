@@ -231,6 +231,33 @@ auv_status auv_resample_kriging(const float *src, const auv_grid_desc *s,
                                 float *dst, const auv_grid_desc *d, double range,
                                 auv_stream stream);
 
+/* ------------------------------------------------- no device allocation --
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * auv_grid_idw_noalloc computes what auv_bin_points(grid, x, y, z, n,
+ * params->radius, bin_log2, ...) followed by auv_interp_idw(grid, bins,
+ * params, z_out, cnt_out, nn_idx_out, nn_z_out, ...) compute (same
+ * definition, tolerance, exact counts and nearest picks), but the bins and
+ * the binning scratch live in a static device array of
+ * AUV_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends.  It calls no hipMalloc, hipFree or other
+ * allocating routine; the caller still passes inputs (device float64 x, y, z,
+ * n each) and outputs (device [ny][nx]; cnt_out, nn_idx_out, nn_z_out
+ * nullable).  Work is enqueued on `stream` (of the current device).
+ * Every call on one GPU shares that GPU's array and overwrites it: calls that
+ * overlap on one GPU (different streams, or threads, without ordering between
+ * them) race.  Serialise them on one stream or with events.
+ * Errors: as auv_bin_points and auv_interp_idw, plus AUV_ERR_BUDGET when
+ * auv_bin_workspace_size(grid, n, params->radius, bin_log2) exceeds
+ * AUV_NOALLOC_SCRATCH_BYTES (the 2M-sounding swath on a 4096^2 grid at 2 m
+ * with a 6 m radius needs about 149 MB). */
+#define AUV_NOALLOC_SCRATCH_BYTES ((size_t)160 << 20)
+auv_status auv_grid_idw_noalloc(const auv_grid *grid, const double *x, const double *y,
+                                const double *z, int64_t n, int32_t bin_log2,
+                                const auv_idw_params *params, float *z_out, int32_t *cnt_out,
+                                int32_t *nn_idx_out, float *nn_z_out, auv_stream stream);
+
 /* ------------------------------------------------------------ batches --
  * Many independent, uneven gridding problems ("items") run as one unit: one
  * set of batched binning launches and one persistent IDW launch per kernel

@@ -109,6 +109,8 @@ def load_library(path: str = LIB_PATH):
         "auv_bins_destroy": ([vp], None),
         "auv_interp_idw": ([vp, vp, P(auv_idw_params), vp, vp, vp, vp, vp], ctypes.c_int),
         "auv_interp_nearest": ([vp, vp, d, vp, vp, vp], ctypes.c_int),
+        "auv_grid_idw_noalloc": ([vp, vp, vp, vp, i64, i32, P(auv_idw_params), vp, vp, vp, vp,
+                                  vp], ctypes.c_int),
         "auv_resample_bilinear": ([vp, P(auv_grid_desc), vp, P(auv_grid_desc), vp],
                                   ctypes.c_int),
         "auv_resample_bicubic": ([vp, P(auv_grid_desc), vp, P(auv_grid_desc), vp],
@@ -303,6 +305,28 @@ def auv_interp_idw(grid: Grid, bins: Bins, params: auv_idw_params, z_out: torch.
                               _dev(nn_idx_out, torch.int32, "nn_idx_out", m),
                               _dev(nn_z_out, torch.float32, "nn_z_out", m),
                               _stream(stream)))
+
+
+def auv_grid_idw_noalloc(grid: Grid, x: torch.Tensor, y: torch.Tensor, z: torch.Tensor,
+                         bin_log2: int, params: auv_idw_params, z_out: torch.Tensor,
+                         cnt_out=None, nn_idx_out=None, nn_z_out=None, stream=None):
+    """Binning + IDW with the bins in the library's static device scratch
+    (no device allocation; AUV_NOALLOC_SCRATCH_BYTES bytes per GPU)."""
+    lib = load_library()
+    n = int(x.numel())
+    m = grid.nx * grid.ny
+    _check(lib.auv_grid_idw_noalloc(grid.handle, _dev(x, torch.float64, "x", n),
+                                    _dev(y, torch.float64, "y", n),
+                                    _dev(z, torch.float64, "z", n), n, int(bin_log2),
+                                    ctypes.byref(params),
+                                    _dev(z_out, torch.float32, "z_out", m),
+                                    _dev(cnt_out, torch.int32, "cnt_out", m),
+                                    _dev(nn_idx_out, torch.int32, "nn_idx_out", m),
+                                    _dev(nn_z_out, torch.float32, "nn_z_out", m),
+                                    _stream(stream)))
+
+
+AUV_NOALLOC_SCRATCH_BYTES = 160 << 20
 
 
 def auv_interp_nearest(grid: Grid, bins: Bins, radius: float, idx_out: torch.Tensor,

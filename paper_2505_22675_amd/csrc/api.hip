@@ -74,6 +74,57 @@ int32_t node_lattice_host(int32_t j, double d)
 }
 
 }  // namespace
+
+auv_status bin_into(const auv_grid *grid, const double *x, const double *y, const double *z,
+                    int64_t n, double radius, int32_t bin_log2, void *ws, size_t ws_bytes,
+                    hipStream_t stream, auv_bins *b)
+{
+    if (!grid)
+        return fail(AUV_ERR_INVALID, "grid is null");
+    if (n < 0 || n >= INT32_MAX)
+        return fail(AUV_ERR_INVALID, "n must be in [0, 2^31-1)");
+    BinGeom geom;
+    AUV_TRY(bin_geometry(grid, radius, bin_log2, &geom));
+    BinWorkspace w;
+    const size_t need = bin_workspace_layout(n, geom, static_cast<char *>(ws), &w);
+    if (ws_bytes < need)
+        return fail(AUV_ERR_BUDGET, "workspace smaller than auv_bin_workspace_size");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+        return fail(AUV_ERR_INVALID, "workspace must be 256-byte aligned");
+    AUV_TRY(check_device_ptr(ws, "workspace"));
+    if (n > 0) {
+        AUV_TRY(check_device_ptr(x, "x"));
+        AUV_TRY(check_device_ptr(y, "y"));
+        AUV_TRY(check_device_ptr(z, "z"));
+    }
+    AUV_TRY(launch_binning(grid, geom, x, y, z, n, w, stream));
+    b->v.cell_start = w.cell_start;
+    b->v.X = w.X;
+    b->v.Y = w.Y;
+    b->v.res = w.res;
+    b->v.z = w.z;
+    b->v.idx = w.idx;
+    b->v.rec = w.rec;
+    {
+        int bits = 1;
+        while (bits < 31 && (int64_t(1) << bits) < n)
+            ++bits;
+        b->v.idx_bits = bits;
+    }
+    b->v.nbx = geom.nbx;
+    b->v.nby = geom.nby;
+    b->v.halo = geom.halo;
+    b->v.bin_log2 = geom.s;
+    b->v.R = geom.R;
+    b->grid = grid;
+    b->radius = radius;
+    b->n = n;
+    b->stats = w.stats;
+    b->ws = ws;
+    b->ws_bytes = ws_bytes;
+    return AUV_OK;
+}
+
 }  // namespace auv
 
 using namespace auv;
@@ -123,57 +174,15 @@ auv_status auv_bin_points(const auv_grid *grid, const double *x, const double *y
     if (!out)
         return fail(AUV_ERR_INVALID, "out is null");
     *out = nullptr;
-    if (!grid)
-        return fail(AUV_ERR_INVALID, "grid is null");
-    if (n < 0 || n >= INT32_MAX)
-        return fail(AUV_ERR_INVALID, "n must be in [0, 2^31-1)");
-    BinGeom geom;
-    AUV_TRY(bin_geometry(grid, radius, bin_log2, &geom));
-    BinWorkspace w;
-    const size_t need = bin_workspace_layout(n, geom, static_cast<char *>(ws), &w);
-    if (ws_bytes < need)
-        return fail(AUV_ERR_BUDGET, "workspace smaller than auv_bin_workspace_size");
-    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
-        return fail(AUV_ERR_INVALID, "workspace must be 256-byte aligned");
-    AUV_TRY(check_device_ptr(ws, "workspace"));
-    if (n > 0) {
-        AUV_TRY(check_device_ptr(x, "x"));
-        AUV_TRY(check_device_ptr(y, "y"));
-        AUV_TRY(check_device_ptr(z, "z"));
-    }
     auv_bins *b = new (std::nothrow) auv_bins;
     if (!b)
         return fail(AUV_ERR_INVALID, "out of host memory");
-    const auv_status st =
-        launch_binning(grid, geom, x, y, z, n, w, static_cast<hipStream_t>(stream));
+    const auv_status st = bin_into(grid, x, y, z, n, radius, bin_log2, ws, ws_bytes,
+                                   static_cast<hipStream_t>(stream), b);
     if (st != AUV_OK) {
         delete b;
         return st;
     }
-    b->v.cell_start = w.cell_start;
-    b->v.X = w.X;
-    b->v.Y = w.Y;
-    b->v.res = w.res;
-    b->v.z = w.z;
-    b->v.idx = w.idx;
-    b->v.rec = w.rec;
-    {
-        int bits = 1;
-        while (bits < 31 && (int64_t(1) << bits) < n)
-            ++bits;
-        b->v.idx_bits = bits;
-    }
-    b->v.nbx = geom.nbx;
-    b->v.nby = geom.nby;
-    b->v.halo = geom.halo;
-    b->v.bin_log2 = geom.s;
-    b->v.R = geom.R;
-    b->grid = grid;
-    b->radius = radius;
-    b->n = n;
-    b->stats = w.stats;
-    b->ws = ws;
-    b->ws_bytes = ws_bytes;
     *out = b;
     return AUV_OK;
 }

@@ -172,6 +172,11 @@ auv_status launch_binning_batch(const RowItem *d_items, const int32_t *d_hist_of
                                 int32_t sort_blocks, int32_t max_nbx, int32_t max_nby,
                                 hipStream_t st);
 
+// The work of auv_bin_points into a caller-provided handle (no allocation).
+auv_status bin_into(const auv_grid *grid, const double *x, const double *y, const double *z,
+                    int64_t n, double radius, int32_t bin_log2, void *ws, size_t ws_bytes,
+                    hipStream_t stream, auv_bins *b);
+
 auv_status launch_binning(const auv_grid *g, const BinGeom &geom,
                           const double *x, const double *y, const double *z,
                           int64_t n, const BinWorkspace &w, hipStream_t st);
