@@ -452,25 +452,38 @@ def batched_report(ag, dev, reps=20):
     return out
 
 
-def serving_report(ag, dev, duration=3.0, stress=10.0):
+def serving_schedule_for_bench(duration):
+    """The serving requests, generated before the GPU is touched (the vehicles
+    are generated in forked worker processes)."""
+    from gen import serving_schedule
+
+    workers = max(1, min(16, os.cpu_count() or 1))
+    log(f"generating {duration:.0f} s of serving requests ({workers} workers)")
+    t = time.perf_counter()
+    sched = serving_schedule(duration=duration, workers=workers)
+    log(f"serving requests ready: {len(sched[1])} in {time.perf_counter() - t:.1f} s")
+    return sched
+
+
+def serving_report(ag, dev, sched, duration, stress=10.0):
     """16 vehicles (2048^2 grids at 2 m), Poisson requests at 20 Hz per vehicle
     of 2k..50k soundings (a +-60 deg fan at 150 m altitude), replayed in real
     time: FIFO (one request at a time) against continuous batching, at the
-    nominal rate and at `stress` times the rate for the same wall time (the
-    schedule played `stress` times back to back with its arrival times
-    divided, so the percentiles rest on `stress` times as many requests).
-    Latency = completion seen by the session - scheduled arrival."""
+    nominal rate (the whole schedule, `duration` seconds) and at `stress`
+    times the rate (the same schedule with its arrival times divided, lasting
+    duration / stress seconds).  Latency = completion seen by the session -
+    scheduled arrival.  `launches` counts the distinct launches the requests
+    went in (a launch takes at most one request per vehicle)."""
     import numpy as np
     import torch
 
-    from gen import serving_schedule
-
-    log(f"generating {duration:.0f} s of serving requests")
-    grids, reqs = serving_schedule(duration=duration)
+    grids, reqs = sched
     n_req = len(reqs)
     n_snd = int(sum(len(r.x) for r in reqs))
     out = {"workload": f"16 vehicles, 2048^2 grids @ 2 m, Poisson 20 Hz each, 2k..50k "
-                       f"soundings per request, r=6 m p=2 no cap; {duration:.0f} s replay",
+                       f"soundings per request, r=6 m p=2 no cap; {duration:.0f} s replay at "
+                       f"the nominal rate, the same schedule at {stress:.0f}x its rate "
+                       f"({duration / stress:.0f} s)",
            "requests": n_req, "soundings": n_snd}
     for mode, name in ((ag.AUV_SERVE_FIFO, "fifo"), (ag.AUV_SERVE_BATCHED, "batched")):
         for scale in (1.0, stress):
@@ -489,10 +502,9 @@ def serving_report(ag, dev, duration=3.0, stress=10.0):
             gc.disable()
             t0 = sess.now() + 0.05
             tickets = []
-            cycles = max(1, int(round(scale)))
-            plays = [(c, r) for c in range(cycles) for r in reqs]
-            for c, r in plays:
-                ta = t0 + (c * duration + r.t_arrival) / scale
+            plays = reqs
+            for r in plays:
+                ta = t0 + r.t_arrival / scale
                 while True:
                     d = ta - sess.now()
                     if d <= 0:
@@ -505,6 +517,7 @@ def serving_report(ag, dev, duration=3.0, stress=10.0):
             infos = [sess.poll(t) for t in tickets]
             lat = np.array([i.t_done - i.t_arrival for i in infos]) * 1e3
             queue = np.array([i.t_launch - i.t_arrival for i in infos]) * 1e3
+            launches = len({i.t_launch for i in infos})
             late = max(i.t_done for i in infos) - t0
             updates = 0
             for v in range(len(grids)):
@@ -520,7 +533,9 @@ def serving_report(ag, dev, duration=3.0, stress=10.0):
                         "node_updates": updates,
                         "node_updates_per_s": round(updates / late, 1),
                         "requests": len(plays),
-                        "soundings_per_s": round(cycles * n_snd / late, 1)}
+                        "launches": launches,
+                        "requests_per_launch": round(len(plays) / max(launches, 1), 3),
+                        "soundings_per_s": round(n_snd / late, 1)}
             log(f"serving {key}: {len(plays)} requests, p50 {out[key]['p50_ms']:.3f} ms, "
                 f"p99 {out[key]['p99_ms']:.3f} ms, max {out[key]['max_ms']:.3f} ms")
     return out
@@ -538,7 +553,8 @@ def main():
                     help="skip the 256-tile plain-vs-batched comparison")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the 16-vehicle serving replay (FIFO vs continuous batching)")
-    ap.add_argument("--serving-seconds", type=float, default=3.0)
+    ap.add_argument("--serving-seconds", type=float, default=60.0,
+                    help="length of the serving schedule (nominal-rate replay)")
     ap.add_argument("--no-grids", action="store_true",
                     help="skip the grid-A sweep and the grid-B infill protocol")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -557,6 +573,10 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the path would shard by spatial tile with an r-halo)", file=sys.stderr)
         sys.exit(2)
+
+    sched = None
+    if not args.no_serving:
+        sched = serving_schedule_for_bench(args.serving_seconds)
 
     import numpy as np
     import torch
@@ -734,7 +754,8 @@ def main():
 
     serving = None
     if not args.no_serving:
-        serving = serving_report(ag, dev, duration=args.serving_seconds)
+        serving = serving_report(ag, dev, sched, args.serving_seconds)
+        del sched
 
     grid_a = grid_b = None
     if not args.no_grids:

@@ -66,6 +66,27 @@ def _hash01(ix: np.ndarray, iy: np.ndarray, salt: int) -> np.ndarray:
     return (h >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
 
 
+def _corner_values(ix, iy, salt):
+    """Lattice values U[-1, 1] at the four corners (ix, iy), (ix+1, iy),
+    (ix, iy+1), (ix+1, iy+1).  The hash is evaluated once per lattice point of
+    the inputs' bounding box and gathered (same values as hashing each corner
+    directly); very large boxes hash the corners directly."""
+    if ix.size == 0:
+        e = np.zeros(ix.shape)
+        return e, e, e, e
+    ix0, iy0 = int(ix.min()), int(iy.min())
+    nx, ny = int(ix.max()) - ix0 + 2, int(iy.max()) - iy0 + 2
+    if nx * ny > 4 * ix.size + (1 << 16):
+        return (2.0 * _hash01(ix, iy, salt) - 1.0, 2.0 * _hash01(ix + 1, iy, salt) - 1.0,
+                2.0 * _hash01(ix, iy + 1, salt) - 1.0, 2.0 * _hash01(ix + 1, iy + 1, salt) - 1.0)
+    gx = np.arange(nx, dtype=np.int64) + ix0
+    gy = np.arange(ny, dtype=np.int64) + iy0
+    table = (2.0 * _hash01(np.broadcast_to(gx[None, :], (ny, nx)),
+                           np.broadcast_to(gy[:, None], (ny, nx)), salt) - 1.0).ravel()
+    k = (iy - iy0) * nx + (ix - ix0)
+    return table[k], table[k + 1], table[k + nx], table[k + nx + 1]
+
+
 def _fade(t):
     return t * t * t * (t * (t * 6.0 - 15.0) + 10.0)
 
@@ -87,10 +108,7 @@ def value_noise(x, y, seed: int = 2, octaves: int = 5, base_wavelength: float = 
         ix = ix.astype(np.int64)
         iy = iy.astype(np.int64)
         salt = (seed * 0x100000001B3 + o * 0x9E3779B1) & 0xFFFFFFFFFFFFFFFF
-        v00 = 2.0 * _hash01(ix, iy, salt) - 1.0
-        v10 = 2.0 * _hash01(ix + 1, iy, salt) - 1.0
-        v01 = 2.0 * _hash01(ix, iy + 1, salt) - 1.0
-        v11 = 2.0 * _hash01(ix + 1, iy + 1, salt) - 1.0
+        v00, v10, v01, v11 = _corner_values(ix, iy, salt)
         a = v00 + tx * (v10 - v00)
         b = v01 + tx * (v11 - v01)
         acc = acc + amp * (a + ty * (b - a))
@@ -235,47 +253,67 @@ class Request:
     z: np.ndarray
 
 
+def _vehicle_requests(v, seed, duration, rate_hz, n_lo, n_hi, nodes, dx, beams, altitude,
+                      line_spacing, ping_spacing):
+    """Grid and request stream of vehicle v (its own random stream)."""
+    ext = nodes * dx
+    step = 120.0 / beams
+    theta0 = np.deg2rad(-60.0 + (np.arange(beams) + 0.5) * step)
+    rng = np.random.default_rng([seed, v])
+    ox, oy = (v % 4) * 2 * ext, (v // 4) * 2 * ext
+    grid = GridSpec(ox, oy, dx, dx, nodes, nodes)
+    n_lines = max(1, int(ext // line_spacing))
+    lines = (np.arange(n_lines) + 0.5) * line_spacing
+    pings_per_line = int(ext // ping_spacing)
+    t, ping, out = 0.0, 0, []
+    while True:
+        t += rng.exponential(1.0 / rate_hz)
+        if t >= duration:
+            break
+        n = int(rng.integers(n_lo, n_hi + 1))
+        npings = -(-n // beams)
+        ids = ping + np.arange(npings)
+        ping += npings
+        li = (ids // pings_per_line) % n_lines
+        k = ids % pings_per_line
+        py = (k + 0.5) * ping_spacing
+        py = np.where(li % 2 == 0, py, ext - py)
+        jit = rng.uniform(-0.5, 0.5, (npings, beams)) * np.deg2rad(1.0)
+        th = theta0[None, :] + jit
+        xs = (lines[li][:, None] + altitude * np.tan(th)).reshape(-1)[:n] + ox
+        ys = np.broadcast_to(py[:, None], th.shape).reshape(-1)[:n] + oy
+        dpt = seafloor_depth(xs, ys, seed=2)
+        zs = -(dpt + rng.normal(0.0, 1.0, n) * 0.002 * dpt)
+        out.append(Request(v, t, xs.astype(np.float64), ys.astype(np.float64), zs))
+    return grid, out
+
+
+def _vehicle_requests_star(a):
+    return _vehicle_requests(*a)
+
+
 def serving_schedule(n_vehicles=16, duration=60.0, rate_hz=20.0, n_lo=2000,
                      n_hi=50000, seed=5, nodes=2048, dx=2.0, beams=400,
                      altitude=150.0, line_spacing=512.0, ping_spacing=2.0,
-                     max_requests=None):
+                     max_requests=None, workers=1):
     """Per-vehicle Poisson request streams.  Each vehicle owns a nodes^2 grid
     at dx at its own offset in the shared plane and flies its own lawnmower
     (lines `line_spacing` apart, pings `ping_spacing` apart, wrapping around);
     a request of n soundings is ceil(n/beams) consecutive pings of a +-60 deg
     fan at `altitude`, truncated to n.  Returns (grids, requests sorted by
-    arrival)."""
-    ext = nodes * dx
-    grids, reqs = [], []
-    step = 120.0 / beams
-    theta0 = np.deg2rad(-60.0 + (np.arange(beams) + 0.5) * step)
-    for v in range(n_vehicles):
-        rng = np.random.default_rng([seed, v])
-        ox, oy = (v % 4) * 2 * ext, (v // 4) * 2 * ext
-        grids.append(GridSpec(ox, oy, dx, dx, nodes, nodes))
-        n_lines = max(1, int(ext // line_spacing))
-        lines = (np.arange(n_lines) + 0.5) * line_spacing
-        pings_per_line = int(ext // ping_spacing)
-        t, ping = 0.0, 0
-        while True:
-            t += rng.exponential(1.0 / rate_hz)
-            if t >= duration:
-                break
-            n = int(rng.integers(n_lo, n_hi + 1))
-            npings = -(-n // beams)
-            ids = ping + np.arange(npings)
-            ping += npings
-            li = (ids // pings_per_line) % n_lines
-            k = ids % pings_per_line
-            py = (k + 0.5) * ping_spacing
-            py = np.where(li % 2 == 0, py, ext - py)
-            jit = rng.uniform(-0.5, 0.5, (npings, beams)) * np.deg2rad(1.0)
-            th = theta0[None, :] + jit
-            xs = (lines[li][:, None] + altitude * np.tan(th)).reshape(-1)[:n] + ox
-            ys = np.broadcast_to(py[:, None], th.shape).reshape(-1)[:n] + oy
-            dpt = seafloor_depth(xs, ys, seed=2)
-            zs = -(dpt + rng.normal(0.0, 1.0, n) * 0.002 * dpt)
-            reqs.append(Request(v, t, xs.astype(np.float64), ys.astype(np.float64), zs))
+    arrival).  Vehicles draw from independent streams, so `workers` > 1
+    generates them in forked processes with the same result (fork only from a
+    process that has not initialised a GPU)."""
+    args = [(v, seed, duration, rate_hz, n_lo, n_hi, nodes, dx, beams, altitude,
+             line_spacing, ping_spacing) for v in range(n_vehicles)]
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(workers, n_vehicles)) as pool:
+            per = pool.map(_vehicle_requests_star, args, chunksize=1)
+    else:
+        per = [_vehicle_requests(*a) for a in args]
+    grids = [g for g, _ in per]
+    reqs = [r for _, rs in per for r in rs]
     reqs.sort(key=lambda r: (r.t_arrival, r.vehicle))
     if max_requests is not None:
         reqs = reqs[:max_requests]
