@@ -22,6 +22,7 @@
 #include "idw_span_impl.hpp"
 
 #include <algorithm>
+#include <type_traits>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -75,30 +76,49 @@ __device__ inline int pull(int32_t *qhead, int q, int len, int grab)
     return t < len ? t : -1;
 }
 
+// Guided grab size: half of the tiles still unclaimed as last seen by this
+// wave (`seen`, the queue head after its previous grab) spread over the
+// `waves` sharing the queue, at most gmax, at least one.  The grabs shrink
+// toward one tile as the queue drains, so no wave is left with a long run of
+// expensive tiles at the end while the others idle.
+__device__ inline int grab_size(int seen, int len, int gmax, int waves)
+{
+    return max(1, min(gmax, (len - seen) / (2 * waves)));
+}
+
 // Persistent kernels, one per kernel form (the forms' register budgets differ
 // by 2x, so sharing one kernel would halve the occupancy of the sparse form).
 // Each wave starts on the queue of its own XCD and then drains the others.
+// The window kernel is instantiated with the span form (its LDS is the union
+// of both forms' arrays) and with a general power (a second window variant
+// with running log-weight maxima) only when some item needs them: each costs
+// LDS or registers, hence occupancy.
+template <bool kSpan, bool kGeneral>
 __global__ __launch_bounds__(64) void k_idw_batch_window(const IdwItem *__restrict__ items,
                                                          const int2 *__restrict__ work,
                                                          const int32_t *__restrict__ qoff,
                                                          const int32_t *__restrict__ qgrab,
-                                                         int32_t *__restrict__ qhead)
+                                                         int32_t *__restrict__ qhead, int qwaves)
 {
-    // one tile at a time: the span form's LDS and the window form's share
-    // the same bytes
     struct WinLds {
         float2 nd[win::kAcc];
         int cnt[win::kAcc];
         float lo[win::kAcc];
         float hi[win::kAcc];
         unsigned long long key[win::kAcc];
-        float emax[win::kAcc];
+        float emax[kGeneral ? win::kAcc : 1];
         int beg[win::kMaxRows];
         int off[win::kMaxRows + 1];
         int4 rec[128];
     };
+    struct NoSpan {
+        char pad[16];
+    };
+    using SpanLds = typename std::conditional<kSpan, span::Smem<win::kTW, win::kTH>, NoSpan>::type;
+    // one tile at a time: the span form's LDS and the window form's share
+    // the same bytes
     __shared__ union {
-        span::Smem<win::kTW, win::kTH> sp;
+        SpanLds sp;
         WinLds w;
     } lds;
     const win::WinSmem sm{lds.w.nd, lds.w.cnt, lds.w.lo, lds.w.hi, lds.w.key, nullptr, nullptr, nullptr,
@@ -106,9 +126,11 @@ __global__ __launch_bounds__(64) void k_idw_batch_window(const IdwItem *__restri
     const int home = blockIdx.x & (kQueues - 1);
     for (int k = 0; k < kQueues; ++k) {
         const int q = (home + k) & (kQueues - 1);
-        const int len = qoff[q + 1] - qoff[q], grab = qgrab[q];
-        for (int t0 = pull(qhead, q, len, grab); t0 >= 0; t0 = pull(qhead, q, len, grab)) {
-            for (int t = t0; t < min(t0 + grab, len); ++t) {
+        const int len = qoff[q + 1] - qoff[q], gmax = qgrab[q];
+        int seen = 0;
+        for (int g = grab_size(seen, len, gmax, qwaves), t0 = pull(qhead, q, len, g); t0 >= 0;
+             seen = t0 + g, g = grab_size(seen, len, gmax, qwaves), t0 = pull(qhead, q, len, g)) {
+            for (int t = t0; t < min(t0 + g, len); ++t) {
                 // wave-uniform work entry: the item descriptor is then read
                 // with scalar loads into SGPRs instead of vector registers
                 const int2 wv = work[qoff[q] + t];
@@ -118,15 +140,21 @@ __global__ __launch_bounds__(64) void k_idw_batch_window(const IdwItem *__restri
                 // integer powers share one variant (the power is a runtime
                 // value there); a general power needs the window form's
                 // rescaling variant
-                if (it.span) {
-                    __syncthreads();  // the previous tile is finished with the LDS
-                    span::span_tile<3, -1, win::kTW, win::kTH>(it.bv, it.a, it.g, w.y, it.ntx,
-                                                               lds.sp);
-                } else if (it.pmode != 0) {
-                    run_window<-1, 1>(it, w.y, sm);
-                } else {
-                    run_window<0, 1>(it, w.y, sm);
+                if constexpr (kSpan) {
+                    if (it.span) {
+                        __syncthreads();  // the previous tile is finished with the LDS
+                        span::span_tile<3, -1, win::kTW, win::kTH>(it.bv, it.a, it.g, w.y,
+                                                                   it.ntx, lds.sp);
+                        continue;
+                    }
                 }
+                if constexpr (kGeneral) {
+                    if (it.pmode == 0) {
+                        run_window<0, 1>(it, w.y, sm);
+                        continue;
+                    }
+                }
+                run_window<-1, 1>(it, w.y, sm);
             }
         }
     }
@@ -136,14 +164,16 @@ __global__ __launch_bounds__(64) void k_idw_batch_dense(const IdwItem *__restric
                                                         const int2 *__restrict__ work,
                                                         const int32_t *__restrict__ qoff,
                                                         const int32_t *__restrict__ qgrab,
-                                                        int32_t *__restrict__ qhead)
+                                                        int32_t *__restrict__ qhead, int qwaves)
 {
     const int home = blockIdx.x & (kQueues - 1);
     for (int k = 0; k < kQueues; ++k) {
         const int q = (home + k) & (kQueues - 1);
-        const int len = qoff[q + 1] - qoff[q], grab = qgrab[q];
-        for (int t0 = pull(qhead, q, len, grab); t0 >= 0; t0 = pull(qhead, q, len, grab)) {
-            for (int t = t0; t < min(t0 + grab, len); ++t) {
+        const int len = qoff[q + 1] - qoff[q], gmax = qgrab[q];
+        int seen = 0;
+        for (int g = grab_size(seen, len, gmax, qwaves), t0 = pull(qhead, q, len, g); t0 >= 0;
+             seen = t0 + g, g = grab_size(seen, len, gmax, qwaves), t0 = pull(qhead, q, len, g)) {
+            for (int t = t0; t < min(t0 + g, len); ++t) {
                 // wave-uniform work entry (scalar loads of the descriptor)
                 const int2 wv = work[qoff[q] + t];
                 const int2 w = make_int2(__builtin_amdgcn_readfirstlane(wv.x),
@@ -246,6 +276,7 @@ struct auv_batch {
     int32_t hist_blocks = 0, scatter_blocks = 0, sort_blocks = 0, nrow_items = 0;
     int32_t nwork_window = 0, nwork_dense = 0;
     int32_t blocks_window = 0, blocks_dense = 0;  // persistent grid sizes
+    bool any_span = false, any_general = false;    // window items needing those variants
     int32_t max_nbx = 0, max_nby = 0;  // largest bin domain of the row-binned items
     hipStream_t cap_stream2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -444,8 +475,19 @@ auv_status build_tables(auv_batch *b, char *ws)
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    // waves per CU: the window kernel is bound by its LDS (about 10.6 KB per
+    // wave, 15 per CU); the dense kernel gets 8 of its 12 register-bound
+    // slots, leaving room for the window kernel on the concurrent branch
+    // (12 ran the dense items alone 19 % faster but the whole batch 6 % slower)
     b->blocks_window = std::max(1, std::min(b->nwork_window, cus * 16));
     b->blocks_dense = std::max(1, std::min(b->nwork_dense, cus * 8));
+    b->any_span = b->any_general = false;
+    for (int i = 0; i < count; ++i) {
+        if (!b->persistent[i] || b->idw[i].dense)
+            continue;
+        b->any_span = b->any_span || b->idw[i].span;
+        b->any_general = b->any_general || b->idw[i].pmode == 0;
+    }
     std::vector<int32_t> grab(2 * kQueues, 1);
     for (int form = 0; form < 2; ++form) {
         const int per_queue = std::max(1, (form ? b->blocks_dense : b->blocks_window) / kQueues);
@@ -525,13 +567,27 @@ auv_status enqueue_batched(auv_batch *b, char *ws, hipStream_t st)
             AUV_HIP(hipEventRecord(b->ev_fork, st));
             AUV_HIP(hipStreamWaitEvent(b->cap_stream2, b->ev_fork, 0));
             k_idw_batch_dense<<<b->blocks_dense, 64, 0, b->cap_stream2>>>(
-                t.idw, t.work, qoff + kQueues, qgrab + kQueues, t.qhead + kQueues);
+                t.idw, t.work, qoff + kQueues, qgrab + kQueues, t.qhead + kQueues,
+                std::max(1, b->blocks_dense / kQueues));
             AUV_HIP(hipGetLastError());
             AUV_HIP(hipEventRecord(b->ev_join, b->cap_stream2));
         }
-        if (b->nwork_window > 0)
-            k_idw_batch_window<<<b->blocks_window, 64, 0, st>>>(t.idw, t.work, qoff, qgrab,
-                                                               t.qhead);
+        if (b->nwork_window > 0) {
+            const int qw = std::max(1, b->blocks_window / kQueues);
+            const unsigned nb = (unsigned)b->blocks_window;
+            if (b->any_span && b->any_general)
+                k_idw_batch_window<true, true><<<nb, 64, 0, st>>>(t.idw, t.work, qoff, qgrab,
+                                                                  t.qhead, qw);
+            else if (b->any_span)
+                k_idw_batch_window<true, false><<<nb, 64, 0, st>>>(t.idw, t.work, qoff, qgrab,
+                                                                   t.qhead, qw);
+            else if (b->any_general)
+                k_idw_batch_window<false, true><<<nb, 64, 0, st>>>(t.idw, t.work, qoff, qgrab,
+                                                                   t.qhead, qw);
+            else
+                k_idw_batch_window<false, false><<<nb, 64, 0, st>>>(t.idw, t.work, qoff, qgrab,
+                                                                    t.qhead, qw);
+        }
         AUV_HIP(hipGetLastError());
         if (b->nwork_dense > 0)
             AUV_HIP(hipStreamWaitEvent(st, b->ev_join, 0));

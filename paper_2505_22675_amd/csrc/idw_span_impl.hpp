@@ -111,7 +111,9 @@ __device__ void span_tile(const auv_bin_view &bv, const IdwArgs &a, const WinGeo
     const long long R2 = (long long)a.R * a.R;
     const float R2f = (float)R2;
     const int kb = bv.idx_bits;
-    const float invDX = 1.0f / (float)g.DXl, invDY = 1.0f / (float)g.DYl;
+    // estimates with margins (row_span) or corrected exactly in integers
+    const float invDX = __builtin_amdgcn_rcpf((float)g.DXl),
+                invDY = __builtin_amdgcn_rcpf((float)g.DYl);
     // spans per sounding: the window rows padded to a power of two
     int wy_log = 0;
     while ((1 << wy_log) < g.Wy)

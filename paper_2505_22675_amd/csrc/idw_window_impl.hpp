@@ -112,6 +112,30 @@ __device__ inline int wave_sum_i(int v)
 
 __device__ inline int wave_count(bool p) { return __popcll(__ballot(p)); }
 
+// p advanced by `bytes` (a 32-bit offset, so that stores and loads take a
+// scalar base with a 32-bit vector offset).
+template <class T>
+__device__ inline T *byte_at(T *p, uint32_t bytes)
+{
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(p) + bytes);
+}
+template <class T>
+__device__ inline const T *byte_at(const T *p, uint32_t bytes)
+{
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + bytes);
+}
+
+// num / den in FP64 from FP32 sums (den > 0): the hardware reciprocal, one
+// Newton step, the quotient and one correction by its residual.
+__device__ inline double quotient64(float num, float den)
+{
+    const double n = (double)num, d = (double)den;
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    const double q = n * r;
+    return fma(fma(-d, q, n), r, q);
+}
+
 // Non-returning LDS atomics (workgroup scope, relaxed): ds_add_u32,
 // ds_min_u64, ds_min_f32, ds_max_f32.  Used where lanes of one instruction
 // update distinct words, so nothing serialises.
@@ -543,13 +567,17 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
     // sums that are never read (finalisation covers in-grid nodes only).
     static_assert(kTW == 16 && kTH == 16, "the packed tile test assumes 16 x 16 tiles");
     uint32_t pc[kChunks];
+    // c / Wx for c < 256 by a float product: (c + 1/2) / Wx stays at least
+    // 1/512 from an integer, far beyond the reciprocal's rounding
+    const float invWx = __builtin_amdgcn_rcpf((float)g.Wx);
 #pragma unroll
     for (int t = 0; t < kChunks; ++t) {
         const int c = t * 64 + lane;
         const bool v = c < g.ncells;
+        const int cq = (int)(((float)c + 0.5f) * invWx);
         // an unused lane gets a cell far outside any tile
-        ci[t] = v ? c / g.Wx : -100000;
-        cj[t] = v ? c - (c / g.Wx) * g.Wx : -100000;
+        ci[t] = v ? cq : -100000;
+        cj[t] = v ? c - cq * g.Wx : -100000;
         iD[t] = sext23(v ? ci[t] * g.DYl : 0);
         jD[t] = sext23(v ? cj[t] * g.DXl : 0);
         qo[t] = v ? ci[t] * kRS + cj[t] : 0;
@@ -582,7 +610,9 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
     const int nbx_row = min(bv.nbx - 1, (Xt0 + (tw - 1) * g.DXl + R + hB) >> s) - bx_lo + 1;
     const int by_lo = max(0, (Yt0 - R + hB) >> s);
     const int nrows = min(bv.nby - 1, (Yt0 + (th - 1) * g.DYl + R + hB) >> s) - by_lo + 1;
-    const float invDX = 1.0f / (float)g.DXl, invDY = 1.0f / (float)g.DYl;
+    // estimates only (the window origin is corrected exactly in integers)
+    const float invDX = __builtin_amdgcn_rcpf((float)g.DXl),
+                invDY = __builtin_amdgcn_rcpf((float)g.DYl);
 
     float zref = 0.0f;
     bool have_ref = false;
@@ -857,31 +887,40 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
         } else {
             const bool over = act && kcap > 0 && cnt > kcap;
             if (act && !over) {
-                const int64_t o = (int64_t)(ta0 + la) * a.nx + tb0 + lb;
+                // outputs: the tile's first node as a scalar base, 32-bit
+                // byte offsets per lane (rows of the tile lie within 2^30
+                // nodes of it)
+                const size_t tbase = (size_t)ta0 * a.nx + tb0;
+                const uint32_t ob = (uint32_t)(la * a.nx + lb) << 2;
                 if (kMode & 2) {
                     if (a.nn_idx_out)
-                        a.nn_idx_out[o] = cnt > 0 ? bi : -1;
+                        *byte_at(a.nn_idx_out + tbase, ob) = cnt > 0 ? bi : -1;
                     if (a.nn_z_out) {
                         float bz;
                         if constexpr (kPacked)
-                            bz = cnt > 0 ? __int_as_float(bv.rec[bi].w) : NAN;
+                            bz = cnt > 0 ? __int_as_float(byte_at(bv.rec, (uint32_t)bi << 4)->w)
+                                         : NAN;
                         else
                             bz = cnt > 0 ? s_bz[q] : NAN;
-                        a.nn_z_out[o] = bz;
+                        *byte_at(a.nn_z_out + tbase, ob) = bz;
                     }
                 }
                 if constexpr (kIdw) {
                     if (a.cnt_out)
-                        a.cnt_out[o] = cnt;
+                        *byte_at(a.cnt_out + tbase, ob) = cnt;
                     // a hit (best D^2 == 0) carries a dominant weight, so the
                     // ratio is the mean of the hits, and it beats min_pts
                     const bool hole = cnt == 0 || (cnt < a.min_pts && !hit);
                     const float2 nd = s_nd[q];
-                    // the quotient and the return to absolute depth in FP64,
-                    // clamped to the members' depths, rounded once to FP32
-                    const double v = (double)zref + (double)nd.x / (double)nd.y;
-                    a.z_out[o] = hole ? NAN
-                                      : (float)fmin(fmax(v, (double)s_lo[q]), (double)s_hi[q]);
+                    // the quotient num / den and the return to absolute depth
+                    // in FP64 (the hardware reciprocal refined by a Newton
+                    // step, then one residual correction of the quotient),
+                    // rounded once to FP32 and clamped to the members' depths
+                    // (FP32 values, and rounding is monotonic, so this equals
+                    // clamping before the rounding)
+                    const float v = (float)((double)zref + quotient64(nd.x, nd.y));
+                    *byte_at(a.z_out + tbase, ob) =
+                        hole ? NAN : fminf(fmaxf(v, s_lo[q]), s_hi[q]);
                 }
             }
             unsigned long long om = __ballot(over);
