@@ -79,6 +79,14 @@ def valu_from_profile(kernel: str):
     return rec[kernel][0]
 
 
+LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9    # FP32/INT32 lane operations per second, not packed
+ALU_OPS_PER_PAIR = 10                    # exact D^2 (4 mul, 2 add), compare, weight, 2 accumulates
+
+
+def profile_source(fname: str, kernel: str) -> str:
+    return f"profiles/{fname} (sources digest {kernel_source_digest(kernel)})"
+
+
 def traffic_from_profile(kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by the copy-kernel calibration).
@@ -342,8 +350,8 @@ def precision_report(ag, dev):
     log("precision variants on UTM-scale coordinates")
     s = workload_cfg4()
     og = oracle.Grid(s.grid.x0, s.grid.y0, s.grid.dx, s.grid.dy, s.grid.nx, s.grid.ny)
-    oz, oc, _ = oracle.idw(og, s.x, s.y, s.z, s.radius, s.power, s.min_pts, s.max_pts,
-                           bin_log2=19, nthreads=host_threads())
+    oz, oc, onn = oracle.idw(og, s.x, s.y, s.z, s.radius, s.power, s.min_pts, s.max_pts,
+                             bin_log2=19, nthreads=host_threads())
     grid = ag.auv_grid_create(s.grid)
     x, y, z = (torch.from_numpy(a).to(dev) for a in (s.x, s.y, s.z))
     bins = ag.auv_bin_points(grid, x, y, z, s.radius, 0)
@@ -352,7 +360,7 @@ def precision_report(ag, dev):
              ag.AUV_P_FP32_ABSOLUTE: "fp32_absolute"}
     for prec, name in names.items():
         res = ag.grid_idw(grid, bins, power=s.power, min_pts=s.min_pts, max_pts=s.max_pts,
-                          with_counts=True, precision=prec)
+                          with_counts=True, with_nearest=True, precision=prec)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -362,13 +370,25 @@ def precision_report(ag, dev):
         e1.record()
         torch.cuda.synchronize()
         gz = res["z"].cpu().numpy().astype(np.float64)
+        gc = res["cnt"].cpu().numpy()
+        gn = res["nn_idx"].cpu().numpy()
         both = ~np.isnan(gz) & ~np.isnan(oz)
         err = np.abs(gz[both] - oz[both])
         rel = err / np.abs(oz[both])
+        # nodes whose neighbour set matches the oracle's (same count and same
+        # nearest member): their error is the variant's arithmetic; the rest
+        # flipped a member across the radius or reordered the nearest
+        same = (gc == oc) & (gn == onn)
+        sm = same[both]
+
+        def stats(e):
+            return ({"nodes": int(e.size), "max_abs_m": float(e.max()),
+                     "rms_m": float(np.sqrt((e ** 2).mean()))} if e.size else {"nodes": 0})
         out[name] = {"max_abs_m": float(err.max()), "rms_m": float(np.sqrt((err ** 2).mean())),
                      "max_rel": float(rel.max()),
                      "nan_mask_mismatch": int((np.isnan(gz) != np.isnan(oz)).sum()),
-                     "count_mismatch": int((res["cnt"].cpu().numpy() != oc).sum()),
+                     "count_mismatch": int((gc != oc).sum()),
+                     "same_neighbours": stats(err[sm]), "flipped_neighbours": stats(err[~sm]),
                      "idw_ms": round(e0.elapsed_time(e1) / 5, 4)}
         log(f"  {name}: {out[name]}")
     return out
@@ -428,6 +448,17 @@ def batched_report(ag, dev, reps=20):
 
     plain_med, plain_min = timed(plain.launch_plain)
     batch_med, batch_min = timed(tuned.launch)
+    # selected pairs of every tile (per-item IDW with counts, after timing)
+    pairs = {"dense": 0, "sparse": 0}
+    for k, s_ in enumerate(tiles):
+        g_ = ag.auv_grid_create(s_.grid)
+        x_, y_, z_ = keep[k][:3]
+        b_ = ag.auv_bin_points(g_, x_, y_, z_, s_.radius, 0)
+        r_ = ag.grid_idw(g_, b_, power=s_.power, min_pts=s_.min_pts, max_pts=s_.max_pts,
+                         with_counts=True)
+        form = "dense" if plans[k][1] == ag.AUV_ALGO_DENSE else "sparse"
+        pairs[form] += int(r_["cnt"].sum(dtype=torch.int64).item())
+        del r_, b_
     log(f"batched workload: plain {plain_med:.3f} ms, batched {batch_med:.3f} ms "
         f"(median of {reps})")
     alg_bytes = n_pts * 24 + n_nodes * 12
@@ -442,6 +473,9 @@ def batched_report(ag, dev, reps=20):
         "plain_nodes_per_s": round(n_nodes / (plain_med * 1e-3), 1),
         "batched_nodes_per_s": round(n_nodes / (batch_med * 1e-3), 1),
         "batched_hbm_frac": round(alg_bytes / (batch_med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "selected_pairs": pairs,
+        "batched_alu_frac": round(sum(pairs.values()) * ALU_OPS_PER_PAIR / (batch_med * 1e-3)
+                                  / LANE_OPS_PEAK, 4),
         "algorithmic_bytes": int(alg_bytes),
         "autotune_s": round(tune_s, 2), "tune_table": table,
         "dense_tiles": int(sum(a == ag.AUV_ALGO_DENSE for _, a in plans)),
@@ -656,13 +690,33 @@ def main():
                 "avg_launch_ms": round(float(dur[dom]), 5)}
 
     roofline["traffic"] = traffic_from_profile(kernel_names[dom])
-    # the kernel is bound by VALU issue, not bytes: its profiled instruction
-    # count over the live launch time against the chip's issue rate
+    roofline["traffic_source"] = (profile_source("hbm_traffic_swath2M.md", kernel_names[dom])
+                                  if roofline["traffic"] is not None else None)
+    # the algorithmic ALU fraction: in-radius pairs (every selected member of
+    # every node, counted by one extra IDW launch with counts) times the ops a
+    # pair needs, over the launch time, against the chip's lane-op rate
+    if dom == "idw":
+        cnt = torch.empty(shape, dtype=torch.int32, device=dev)
+        ag.auv_interp_idw(grid, bins, params, z_out, cnt, nn_idx, nn_z, stream=stream)
+        torch.cuda.synchronize()
+        pairs = int(cnt.sum(dtype=torch.int64).item())
+        del cnt
+        alu_ops = pairs * ALU_OPS_PER_PAIR / (dur[dom] * 1e-3)
+        roofline["alu"] = {"pairs": pairs, "ops_per_pair": ALU_OPS_PER_PAIR,
+                           "achieved_lane_ops_per_s": round(alu_ops, 1),
+                           "peak_lane_ops_per_s": LANE_OPS_PEAK,
+                           "frac": round(alu_ops / LANE_OPS_PEAK, 4)}
+        rel = max(("hbm", roofline["frac"]), ("alu", roofline["alu"]["frac"]),
+                  key=lambda t: t[1])
+        roofline["relevant"] = {"bound": rel[0], "frac": rel[1]}
+    # issue rate: the profiled VALU instruction count (overhead included) over
+    # the live launch time against the chip's issue rate
     valu = valu_from_profile(kernel_names[dom])
     roofline["valu_issue"] = None if valu is None else {
         "instructions": valu, "achieved_per_s": round(valu / (dur[dom] * 1e-3), 1),
         "peak_per_s": VALU_ISSUE_PEAK,
-        "frac": round(valu / (dur[dom] * 1e-3) / VALU_ISSUE_PEAK, 4)}
+        "frac": round(valu / (dur[dom] * 1e-3) / VALU_ISSUE_PEAK, 4),
+        "source": profile_source("valu_issue_swath2M.md", kernel_names[dom])}
 
     # the practical ceiling in this run: a 256 MiB device-to-device copy
     ca = torch.ones(64 << 20, dtype=torch.float32, device=dev)

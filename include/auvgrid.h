@@ -308,16 +308,21 @@ auv_status auv_batch_launch_plain(auv_batch *batch, void *ws, size_t ws_bytes,
 
 /* Autotuner: group the items into classes (expected soundings per disk and
  * grid side, both bucketed by powers of two), time the candidate (bin size,
- * kernel form) pairs on one representative item per class, and write the
- * fastest per class to tune_path (a small text table).  Synchronises
+ * kernel form) pairs at the form's default node tile on one representative
+ * item per class, then the winner with the form's other node tiles (window
+ * form 16 x 16 or 16 x 8 nodes per wave; dense form 8 x 8, 16 x 4 or 4 x 16),
+ * and write the fastest per class to tune_path (a small text table:
+ * "class <dens> <side> bin_log2 <s> algo <a> tile <w> <h> ms <t>"; tables
+ * without the tile fields stand for the default tiles).  Synchronises
  * `stream`; uses `ws` (at least auv_batch_workspace_size of a batch planned
  * from the same items) as scratch, and overwrites the items' outputs. */
 auv_status auv_batch_autotune(const auv_batch_item *items, int32_t count, void *ws,
                               size_t ws_bytes, auv_stream stream, const char *tune_path);
 
-/* Per-item plan actually used (for reports): bin_log2 and kernel form. */
+/* Per-item plan actually used (for reports): bin_log2, kernel form and node
+ * tile per wave (columns, rows).  Every pointer is nullable. */
 auv_status auv_batch_item_plan(const auv_batch *batch, int32_t item, int32_t *bin_log2,
-                               int32_t *algo);
+                               int32_t *algo, int32_t *tile_w, int32_t *tile_h);
 
 void auv_batch_destroy(auv_batch *batch);
 

@@ -123,7 +123,7 @@ def load_library(path: str = LIB_PATH):
         "auv_batch_launch_plain": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
         "auv_batch_autotune": ([P(auv_batch_item), i32, vp, ctypes.c_size_t, vp,
                                 ctypes.c_char_p], ctypes.c_int),
-        "auv_batch_item_plan": ([vp, i32, P(i32), P(i32)], ctypes.c_int),
+        "auv_batch_item_plan": ([vp, i32, P(i32), P(i32), P(i32), P(i32)], ctypes.c_int),
         "auv_batch_destroy": ([vp], None),
         "auv_session_budget": ([P(auv_session_desc), P(ctypes.c_size_t), P(ctypes.c_size_t)],
                                ctypes.c_int),
@@ -457,9 +457,14 @@ class Batch:
 
     def item_plan(self, i: int):
         """(bin_log2, algo) the batched form uses for item i."""
-        s, a = ctypes.c_int32(), ctypes.c_int32()
-        _check(_lib.auv_batch_item_plan(self._h, i, ctypes.byref(s), ctypes.byref(a)))
-        return s.value, a.value
+        return self.item_plan_full(i)[:2]
+
+    def item_plan_full(self, i: int):
+        """(bin_log2, algo, tile_w, tile_h) the batched form uses for item i."""
+        s, a, tw, th = (ctypes.c_int32() for _ in range(4))
+        _check(_lib.auv_batch_item_plan(self._h, i, ctypes.byref(s), ctypes.byref(a),
+                                        ctypes.byref(tw), ctypes.byref(th)))
+        return s.value, a.value, tw.value, th.value
 
     def close(self):
         if self._h:

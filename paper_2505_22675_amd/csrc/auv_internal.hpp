@@ -199,6 +199,9 @@ struct IdwArgs {
     bool dense;               // use the dense (ring search, top-k) form
     bool span;                // sparse: the span form where it applies
     int32_t pmode;            // 1, 2, 3: integer power (fast weights), 0: general
+    int32_t tile_w, tile_h;   // nodes per wave tile (0: the form's default): window
+                              // form 16 x 16 or 16 x 8; dense form any power-of-two
+                              // shape of 64 nodes (8 x 8, 16 x 4, 4 x 16, ...)
     float *z_out;
     int32_t *cnt_out;
     int32_t *nn_idx_out;

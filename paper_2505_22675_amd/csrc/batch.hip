@@ -230,8 +230,37 @@ bool dense_allowed(const auv_batch_item &it)
 
 struct Choice {
     int32_t bin_log2;
-    int32_t algo;  // AUV_ALGO_SPARSE or AUV_ALGO_DENSE
+    int32_t algo;                // AUV_ALGO_SPARSE or AUV_ALGO_DENSE
+    int32_t tile_w = 0, tile_h = 0;  // node tile per wave (0: the form's default)
 };
+
+// Default node tile of a form.
+Choice with_default_tile(Choice c)
+{
+    c.tile_w = c.algo == AUV_ALGO_DENSE ? dense::kDT : win::kTW;
+    c.tile_h = c.algo == AUV_ALGO_DENSE ? dense::kDT : win::kTH;
+    return c;
+}
+
+// The other node tiles the autotuner may try for a (bin size, form) choice.
+std::vector<Choice> tile_variants(const Choice &c)
+{
+    std::vector<Choice> v;
+    if (c.algo == AUV_ALGO_DENSE) {
+        for (int tw : {16, 4}) {
+            Choice d = c;
+            d.tile_w = tw;
+            d.tile_h = 64 / tw;
+            v.push_back(d);
+        }
+    } else {
+        Choice d = c;
+        d.tile_w = win::kTW;
+        d.tile_h = 8;
+        v.push_back(d);
+    }
+    return v;
+}
 
 // Candidate (bin size, form) pairs the autotuner may time for an item.
 std::vector<Choice> candidates(const auv_batch_item &it, int32_t sR)
@@ -264,6 +293,7 @@ struct auv_batch {
     std::vector<auv::BinGeom> geom;        // batched form
     std::vector<auv::BinGeom> geom_plain;  // plain form
     std::vector<int32_t> algo;             // batched form
+    std::vector<auv::Choice> tile;         // batched form: node tile per wave
     std::vector<size_t> slice_off;         // per-item workspace slice
     std::vector<size_t> slice_size;
     std::vector<uint8_t> persistent;       // covered by the persistent kernel
@@ -313,7 +343,7 @@ auv_status validate_item(const auv_batch_item &it, int i)
 
 // Build the bin view and IDW arguments of item i with its workspace slice.
 void item_views(const auv_batch *b, int i, char *ws, const BinGeom &geom, int32_t algo,
-                BinWorkspace *w, auv_bin_view *bv, IdwArgs *a)
+                BinWorkspace *w, auv_bin_view *bv, IdwArgs *a, Choice tile = Choice{0, 0})
 {
     const auv_batch_item &it = b->items[i];
     bin_workspace_layout(it.n, geom, ws + b->slice_off[i], w);
@@ -359,6 +389,8 @@ void item_views(const auv_batch *b, int i, char *ws, const BinGeom &geom, int32_
     x.dense = algo == AUV_ALGO_DENSE;
     x.span = algo == AUV_ALGO_SPAN;
     x.pmode = pmode_of(it.params.power);
+    x.tile_w = tile.tile_w;
+    x.tile_h = tile.tile_h;
     *a = x;
 }
 
@@ -383,11 +415,49 @@ std::map<ClassKey, Choice> read_tune(const char *path)
         ClassKey key;
         Choice c;
         double ms;
-        if (is >> tag >> key.dens >> key.side >> k1 >> c.bin_log2 >> k2 >> c.algo && tag == "class")
+        if (is >> tag >> key.dens >> key.side >> k1 >> c.bin_log2 >> k2 >> c.algo && tag == "class") {
+            std::string k3;
+            int tw = 0, th = 0;
+            if (is >> k3 && k3 == "tile" && is >> tw >> th) {
+                c.tile_w = tw;
+                c.tile_h = th;
+            }
             t[key] = c;
+        }
         (void)ms;
     }
     return t;
+}
+
+// The persistent kernels' descriptor of one item; false when they do not
+// cover it (window over 64 cells, key over 64 bits, cap above the dense limit).
+bool make_idw_item(const auv_batch_item &it, const auv_bin_view &bv, const IdwArgs &a,
+                   int32_t algo, IdwItem *out)
+{
+    IdwItem d{};
+    d.bv = bv;
+    d.a = a;
+    d.pmode = pmode_of(it.params.power);
+    d.dense = algo == AUV_ALGO_DENSE;
+    d.span = 0;
+    bool ok = true;
+    if (d.dense) {
+        ok = it.params.max_pts >= 1 && it.params.max_pts <= kBatchDenseK;
+        const int tw = dense::dense_tile_w(a), th = 64 / tw;
+        d.ntx = (it.grid.nx + tw - 1) / tw;
+        d.ntiles = d.ntx * ((it.grid.ny + th - 1) / th);
+    } else {
+        ok = window_geometry(a, &d.g) && d.g.nchunks == 1;
+        const unsigned __int128 top = (unsigned __int128)((unsigned long long)a.R * a.R)
+                                      << bv.idx_bits;
+        ok = ok && top < ((unsigned __int128)1 << 64);
+        d.span = ok && a.span && span::span_ok(bv, a, d.g, d.pmode) ? 1 : 0;
+        const int th = win::tile_rows(a);
+        d.ntx = (it.grid.nx + win::kTW - 1) / win::kTW;
+        d.ntiles = d.ntx * ((it.grid.ny + th - 1) / th);
+    }
+    *out = d;
+    return ok;
 }
 
 // Build the device tables for workspace `ws` (host copies kept in the batch).
@@ -405,7 +475,7 @@ auv_status build_tables(auv_batch *b, char *ws)
         BinWorkspace w;
         auv_bin_view bv;
         IdwArgs a;
-        item_views(b, i, ws, b->geom[i], b->algo[i], &w, &bv, &a);
+        item_views(b, i, ws, b->geom[i], b->algo[i], &w, &bv, &a, b->tile[i]);
         if (row_path_ok(b->geom[i])) {
             b->rows[b->row_items.size()] =
                 make_row_item(&b->grids[i], b->geom[i], it.x, it.y, it.z, it.n, w);
@@ -417,26 +487,7 @@ auv_status build_tables(auv_batch *b, char *ws)
             b->max_nby = std::max(b->max_nby, b->geom[i].nby);
         }
         IdwItem &d = b->idw[i];
-        d.bv = bv;
-        d.a = a;
-        d.pmode = pmode_of(it.params.power);
-        d.dense = b->algo[i] == AUV_ALGO_DENSE;
-        d.span = 0;
-        bool ok = true;
-        if (d.dense) {
-            ok = it.params.max_pts >= 1 && it.params.max_pts <= kBatchDenseK;
-            d.ntx = (it.grid.nx + 7) / 8;
-            d.ntiles = d.ntx * ((it.grid.ny + 7) / 8);
-        } else {
-            ok = window_geometry(a, &d.g) && d.g.nchunks == 1;
-            const unsigned __int128 top = (unsigned __int128)((unsigned long long)a.R * a.R)
-                                          << bv.idx_bits;
-            ok = ok && top < ((unsigned __int128)1 << 64);
-            d.span = ok && a.span && span::span_ok(bv, a, d.g, d.pmode) ? 1 : 0;
-            d.ntx = (it.grid.nx + win::kTW - 1) / win::kTW;
-            d.ntiles = d.ntx * ((it.grid.ny + win::kTH - 1) / win::kTH);
-        }
-        ok = ok && row_path_ok(b->geom[i]);
+        const bool ok = make_idw_item(it, bv, a, b->algo[i], &d) && row_path_ok(b->geom[i]);
         b->persistent[i] = ok ? 1 : 0;
         cost[i] = (double)it.n + (double)it.grid.nx * it.grid.ny * (d.dense ? 4.0 : 1.0);
     }
@@ -539,6 +590,22 @@ size_t tables_size(size_t count, size_t max_tiles)
            align256(sizeof(int2) * std::max<size_t>(max_tiles, 1));
 }
 
+void launch_batch_window(int blocks, bool any_span, bool any_general, const IdwItem *idw,
+                         const int2 *work, const int32_t *qoff, const int32_t *qgrab,
+                         int32_t *qhead, hipStream_t st)
+{
+    const int qw = std::max(1, blocks / kQueues);
+    const unsigned nb = (unsigned)blocks;
+    if (any_span && any_general)
+        k_idw_batch_window<true, true><<<nb, 64, 0, st>>>(idw, work, qoff, qgrab, qhead, qw);
+    else if (any_span)
+        k_idw_batch_window<true, false><<<nb, 64, 0, st>>>(idw, work, qoff, qgrab, qhead, qw);
+    else if (any_general)
+        k_idw_batch_window<false, true><<<nb, 64, 0, st>>>(idw, work, qoff, qgrab, qhead, qw);
+    else
+        k_idw_batch_window<false, false><<<nb, 64, 0, st>>>(idw, work, qoff, qgrab, qhead, qw);
+}
+
 // Enqueue the whole batched form on `st` (captured by the caller).
 auv_status enqueue_batched(auv_batch *b, char *ws, hipStream_t st)
 {
@@ -554,7 +621,7 @@ auv_status enqueue_batched(auv_batch *b, char *ws, hipStream_t st)
         BinWorkspace w;
         auv_bin_view bv;
         IdwArgs a;
-        item_views(b, i, ws, b->geom[i], b->algo[i], &w, &bv, &a);
+        item_views(b, i, ws, b->geom[i], b->algo[i], &w, &bv, &a, b->tile[i]);
         const auv_batch_item &it = b->items[i];
         AUV_TRY_S(launch_binning(&b->grids[i], b->geom[i], it.x, it.y, it.z, it.n, w, st));
     }
@@ -572,22 +639,9 @@ auv_status enqueue_batched(auv_batch *b, char *ws, hipStream_t st)
             AUV_HIP(hipGetLastError());
             AUV_HIP(hipEventRecord(b->ev_join, b->cap_stream2));
         }
-        if (b->nwork_window > 0) {
-            const int qw = std::max(1, b->blocks_window / kQueues);
-            const unsigned nb = (unsigned)b->blocks_window;
-            if (b->any_span && b->any_general)
-                k_idw_batch_window<true, true><<<nb, 64, 0, st>>>(t.idw, t.work, qoff, qgrab,
-                                                                  t.qhead, qw);
-            else if (b->any_span)
-                k_idw_batch_window<true, false><<<nb, 64, 0, st>>>(t.idw, t.work, qoff, qgrab,
-                                                                   t.qhead, qw);
-            else if (b->any_general)
-                k_idw_batch_window<false, true><<<nb, 64, 0, st>>>(t.idw, t.work, qoff, qgrab,
-                                                                   t.qhead, qw);
-            else
-                k_idw_batch_window<false, false><<<nb, 64, 0, st>>>(t.idw, t.work, qoff, qgrab,
-                                                                    t.qhead, qw);
-        }
+        if (b->nwork_window > 0)
+            launch_batch_window(b->blocks_window, b->any_span, b->any_general, t.idw, t.work,
+                                qoff, qgrab, t.qhead, st);
         AUV_HIP(hipGetLastError());
         if (b->nwork_dense > 0)
             AUV_HIP(hipStreamWaitEvent(st, b->ev_join, 0));
@@ -623,6 +677,7 @@ auv_status auv_batch_plan(const auv_batch_item *items, int32_t count, const char
     b->geom.resize(count);
     b->geom_plain.resize(count);
     b->algo.resize(count);
+    b->tile.resize(count);
     b->slice_off.resize(count);
     b->slice_size.resize(count);
     b->persistent.assign(count, 0);
@@ -651,10 +706,12 @@ auv_status auv_batch_plan(const auv_batch_item *items, int32_t count, const char
             (f->second.algo == AUV_ALGO_SPARSE || dense_allowed(it)))
             c = f->second;
         b->algo[i] = c.algo;
+        b->tile[i] = c.tile_w > 0 ? c : with_default_tile(c);
         st = bin_geometry(&b->grids[i], it.params.radius, c.bin_log2, &b->geom[i]);
         if (st != AUV_OK) {
             b->geom[i] = b->geom_plain[i];
             b->algo[i] = auto_algo(it);
+            b->tile[i] = with_default_tile(Choice{0, b->algo[i]});
         }
         // slice: the largest layout any form or autotune candidate may use
         size_t need = std::max(bin_workspace_layout(it.n, b->geom[i], nullptr, nullptr),
@@ -689,7 +746,7 @@ auv_status auv_batch_workspace_size(const auv_batch *batch, size_t *bytes)
 }
 
 auv_status auv_batch_item_plan(const auv_batch *batch, int32_t item, int32_t *bin_log2,
-                               int32_t *algo)
+                               int32_t *algo, int32_t *tile_w, int32_t *tile_h)
 {
     if (!batch || item < 0 || item >= (int32_t)batch->items.size())
         return fail(AUV_ERR_INVALID, "bad batch or item");
@@ -697,6 +754,10 @@ auv_status auv_batch_item_plan(const auv_batch *batch, int32_t item, int32_t *bi
         *bin_log2 = batch->geom[item].s;
     if (algo)
         *algo = batch->algo[item];
+    if (tile_w)
+        *tile_w = batch->tile[item].tile_w;
+    if (tile_h)
+        *tile_h = batch->tile[item].tile_h;
     return AUV_OK;
 }
 
@@ -808,51 +869,133 @@ auv_status auv_batch_autotune(const auv_batch_item *items, int32_t count, void *
     hipEvent_t e0, e1;
     AUV_HIP(hipEventCreate(&e0));
     AUV_HIP(hipEventCreate(&e1));
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    // the tables region of the workspace holds the throughput runs' work list
+    size_t work_cap = 0;
+    for (int k = 0; k < count; ++k)
+        work_cap += (size_t)((b->items[k].grid.nx + 7) / 8) * ((b->items[k].grid.ny + 7) / 8);
     std::ostringstream table;
     table << "# auvgrid autotune table: class <log2 disk population> <log2 grid side> "
-             "bin_log2 <s> algo <1 sparse | 2 dense> ms <time>\n";
+             "bin_log2 <s> algo <1 sparse | 2 dense> tile <nodes across> <nodes down> "
+             "ms <time>\n";
     auv_status result = AUV_OK;
     for (const auto &kv : rep) {
         const int i = kv.second;
         const auv_batch_item &it = b->items[i];
-        Choice best{b->geom_plain[i].s, auto_algo(it)};
+        Choice best = with_default_tile(Choice{b->geom_plain[i].s, auto_algo(it)});
         float best_ms = 1e30f;
-        for (const Choice &c : candidates(it, b->geom_plain[i].s)) {
+        // min of three timed runs (after one untimed) of binning + IDW
+        // Time of a candidate in the setting it will run in: binning the item
+        // (min of three runs after one untimed), plus the persistent kernel of
+        // its form over enough repetitions of the item's tiles to fill the
+        // chip (all reading the same bins), per repetition; items the
+        // persistent kernels do not cover get their own IDW launch instead.
+        auto time_choice = [&](const Choice &c, float *out_ms) -> auv_status {
+            *out_ms = 1e30f;
             BinGeom gg;
             if (bin_geometry(&b->grids[i], it.params.radius, c.bin_log2, &gg) != AUV_OK ||
                 (int64_t)gg.nbx * gg.nby > (int64_t)1 << 24 ||
                 bin_workspace_layout(it.n, gg, nullptr, nullptr) > b->slice_size[i])
-                continue;
+                return AUV_OK;
             BinWorkspace w;
             auv_bin_view bv;
             IdwArgs a;
-            item_views(b, i, base, gg, c.algo, &w, &bv, &a);
-            float ms_min = 1e30f;
-            for (int rep_i = 0; rep_i < 4; ++rep_i) {
-                AUV_HIP(hipEventRecord(e0, st));
-                result = launch_binning(&b->grids[i], gg, it.x, it.y, it.z, it.n, w, st);
-                if (result == AUV_OK)
-                    result = launch_idw(bv, a, st);
-                AUV_HIP(hipEventRecord(e1, st));
-                AUV_HIP(hipEventSynchronize(e1));
-                if (result != AUV_OK)
-                    break;
-                float ms = 0.0f;
-                AUV_HIP(hipEventElapsedTime(&ms, e0, e1));
-                if (rep_i > 0)
-                    ms_min = std::min(ms_min, ms);
+            item_views(b, i, base, gg, c.algo, &w, &bv, &a, c);
+            auto min_of_runs = [&](auto &&enqueue, float *best) -> auv_status {
+                *best = 1e30f;
+                for (int rep_i = 0; rep_i < 4; ++rep_i) {
+                    AUV_HIP(hipEventRecord(e0, st));
+                    AUV_TRY_S(enqueue());
+                    AUV_HIP(hipEventRecord(e1, st));
+                    AUV_HIP(hipEventSynchronize(e1));
+                    float ms = 0.0f;
+                    AUV_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if (rep_i > 0)
+                        *best = std::min(*best, ms);
+                }
+                return AUV_OK;
+            };
+            float bin_ms, idw_ms;
+            AUV_TRY_S(min_of_runs(
+                [&] { return launch_binning(&b->grids[i], gg, it.x, it.y, it.z, it.n, w, st); },
+                &bin_ms));
+            IdwItem d;
+            if (!make_idw_item(it, bv, a, c.algo, &d) || !row_path_ok(gg) || d.ntiles < 1) {
+                AUV_TRY_S(min_of_runs([&] { return launch_idw(bv, a, st); }, &idw_ms));
+                *out_ms = bin_ms + idw_ms;
+                return AUV_OK;
             }
+            const int64_t target = (int64_t)cus * 16 * 8;  // tiles: ~8 per resident wave
+            const int copies = (int)std::max<int64_t>(
+                1, std::min<int64_t>((target + d.ntiles - 1) / d.ntiles,
+                                     (int64_t)work_cap / d.ntiles));
+            const int nwork = copies * d.ntiles;
+            std::vector<int2> work(nwork);
+            for (int t = 0; t < nwork; ++t)
+                work[t] = make_int2(0, t % d.ntiles);
+            const int blocks = std::max(1, std::min(nwork, cus * (d.dense ? 8 : 16)));
+            const int per_queue = std::max(1, blocks / kQueues);
+            std::vector<int32_t> offs(2 * kQueues + 1);
+            for (int k = 0; k <= kQueues; ++k)
+                offs[k] = (int32_t)((int64_t)nwork * k / kQueues);
+            for (int k = 0; k < kQueues; ++k)
+                offs[kQueues + 1 + k] =
+                    std::max(1, std::min(16, (offs[k + 1] - offs[k]) / (8 * per_queue)));
+            const Tables t = table_ptrs(b, base);
+            AUV_HIP(hipMemcpyAsync(t.idw, &d, sizeof(d), hipMemcpyHostToDevice, st));
+            AUV_HIP(hipMemcpyAsync(t.work, work.data(), sizeof(int2) * nwork,
+                                   hipMemcpyHostToDevice, st));
+            AUV_HIP(hipMemcpyAsync(t.offs, offs.data(), sizeof(int32_t) * offs.size(),
+                                   hipMemcpyHostToDevice, st));
+            AUV_TRY_S(min_of_runs(
+                [&]() -> auv_status {
+                    k_reset_queues<<<1, 64, 0, st>>>(t.qhead);
+                    if (d.dense)
+                        k_idw_batch_dense<<<blocks, 64, 0, st>>>(t.idw, t.work, t.offs,
+                                                                 t.offs + kQueues + 1, t.qhead,
+                                                                 per_queue);
+                    else
+                        launch_batch_window(blocks, d.span != 0, d.pmode == 0, t.idw, t.work,
+                                            t.offs, t.offs + kQueues + 1, t.qhead, st);
+                    AUV_HIP(hipGetLastError());
+                    return AUV_OK;
+                },
+                &idw_ms));
+            *out_ms = bin_ms + idw_ms / (float)copies;
+            return AUV_OK;
+        };
+        // bin size and form at the form's default tile, then the other node
+        // tiles of the winner
+        for (const Choice &c0 : candidates(it, b->geom_plain[i].s)) {
+            const Choice c = with_default_tile(c0);
+            float ms;
+            result = time_choice(c, &ms);
             if (result != AUV_OK)
                 break;
-            if (ms_min < best_ms) {
-                best_ms = ms_min;
+            if (ms < best_ms) {
+                best_ms = ms;
                 best = c;
+            }
+        }
+        if (result == AUV_OK && best_ms < 1e30f) {
+            for (const Choice &c : tile_variants(best)) {
+                float ms;
+                result = time_choice(c, &ms);
+                if (result != AUV_OK)
+                    break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
             }
         }
         if (result != AUV_OK)
             break;
         table << "class " << kv.first.dens << " " << kv.first.side << " bin_log2 "
-              << best.bin_log2 << " algo " << best.algo << " ms " << best_ms << "\n";
+              << best.bin_log2 << " algo " << best.algo << " tile " << best.tile_w << " "
+              << best.tile_h << " ms " << best_ms << "\n";
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

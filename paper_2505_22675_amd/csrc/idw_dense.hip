@@ -25,7 +25,8 @@ auv_status launch_idw_dense(const auv_bin_view &bv, const IdwArgs &a, int pmode,
 {
     if (a.max_pts < 1 || a.max_pts > 32)
         return fail(AUV_ERR_INVALID, "the dense form needs 1 <= max_pts <= 32");
-    const int ntx = (a.nx + kDT - 1) / kDT, nty = (a.ny + kDT - 1) / kDT;
+    const int TW = dense_tile_w(a), TH = 64 / TW;
+    const int ntx = (a.nx + TW - 1) / TW, nty = (a.ny + TH - 1) / TH;
     switch (a.mode) {
     case 1: launch_k<1>(bv, a, ntx, nty, pmode, st); break;
     case 2: launch_k<2>(bv, a, ntx, nty, pmode, st); break;

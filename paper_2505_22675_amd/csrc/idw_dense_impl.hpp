@@ -191,14 +191,22 @@ __device__ void dense_node(const auv_bin_view &bv, const IdwArgs &a, int b, int 
     }
 }
 
-// One 64-lane wave per 8 x 8 node tile, one node per lane.
+// Node tile of the dense form: tile_w columns (a power of two from 1 to 64,
+// default 8) by 64 / tile_w rows.
+__host__ __device__ inline int dense_tile_w(const IdwArgs &a)
+{
+    return a.tile_w >= 1 && a.tile_w <= 64 && (a.tile_w & (a.tile_w - 1)) == 0 ? a.tile_w : kDT;
+}
+
+// One 64-lane wave per node tile (8 x 8 by default), one node per lane.
 template <int kMode, int KMAX>
 __device__ void dense_tile(const auv_bin_view &bv, const IdwArgs &a, int tile, int ntx,
                            int pmode)
 {
     const int lane = threadIdx.x & 63;
+    const int TW = dense_tile_w(a), TH = 64 / TW;
     const int tx = tile % ntx, ty = tile / ntx;
-    const int b = tx * kDT + (lane % kDT), an = ty * kDT + (lane / kDT);
+    const int b = tx * TW + (lane & (TW - 1)), an = ty * TH + lane / TW;
     if (b < a.nx && an < a.ny)
         dense_node<kMode, KMAX>(bv, a, b, an, pmode);
 }

@@ -39,7 +39,8 @@ bool window_geometry(const IdwArgs &a, WinGeom *g)
 auv_status launch_idw_window(const auv_bin_view &bv, const IdwArgs &a, const WinGeom &g,
                              int pmode, hipStream_t st)
 {
-    const int ntx = (a.nx + kTW - 1) / kTW, nty = (a.ny + kTH - 1) / kTH;
+    const int TH = tile_rows(a);
+    const int ntx = (a.nx + kTW - 1) / kTW, nty = (a.ny + TH - 1) / TH;
     if (a.precision != AUV_P_FP32_REBASE)
         return launch_idw_window_prec(bv, a, g, pmode, st);
     if (a.span && span::span_ok(bv, a, g, pmode)) {

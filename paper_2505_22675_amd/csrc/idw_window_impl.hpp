@@ -43,6 +43,9 @@ constexpr int kMaxRows = 64;         // bin rows per staging pass
 constexpr int kMaxChunks = 4;        // window cells <= 64 * kMaxChunks
 constexpr float kHitW = 0x1p80f;     // weight of a coincident sounding
 
+// Tile rows of the window form: 16 (default) or 8.
+__host__ __device__ inline int tile_rows(const IdwArgs &a) { return a.tile_h == 8 ? 8 : 16; }
+
 __device__ inline int ceil_div(int v, int d)
 {
     return v >= 0 ? (v + d - 1) / d : -((-v) / d);
@@ -549,9 +552,12 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
     int *const s_off = sm.off;
 
     const int lane = threadIdx.x & 63;  // lane within the wave (blocks may hold several)
+    // tile rows: 16 or 8 (the FP16-offset variant measures offsets from the
+    // centre of a 16 x 16 tile, so the variants keep 16)
+    const int TH = kPrec == AUV_P_FP32_REBASE ? tile_rows(a) : kTH;
     const int tx = tile % ntx, ty = tile / ntx;
-    const int tb0 = tx * kTW, ta0 = ty * kTH;
-    const int tw = min(kTW, a.nx - tb0), th = min(kTH, a.ny - ta0);
+    const int tb0 = tx * kTW, ta0 = ty * TH;
+    const int tw = min(kTW, a.nx - tb0), th = min(TH, a.ny - ta0);
     const int Xt0 = g.X0 + tb0 * g.DXl, Yt0 = g.Y0 + ta0 * g.DYl;
     const int R = a.R_stage;          // staging reach (>= the radius)
     const long long R2 = (long long)a.R * a.R;
@@ -565,7 +571,10 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
     // origin are in [0, 16) -- one packed add and one mask test.  Edge tiles
     // are treated as whole 16 x 16 tiles: nodes past the grid edge collect
     // sums that are never read (finalisation covers in-grid nodes only).
-    static_assert(kTW == 16 && kTH == 16, "the packed tile test assumes 16 x 16 tiles");
+    static_assert(kTW == 16 && kTH == 16, "the packed tile test assumes 16-wide tiles of "
+                                          "at most 16 rows");
+    // row half: [0, TH) with TH = 16 or 8; column half: [0, 16)
+    const uint32_t tmask = TH == 16 ? 0xfff0fff0u : 0xfff8fff0u;
     uint32_t pc[kChunks];
     // c / Wx for c < 256 by a float product: (c + 1/2) / Wx stays at least
     // 1/512 from an integer, far beyond the reciprocal's rounding
@@ -743,7 +752,7 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                         typedef unsigned short us2 __attribute__((ext_vector_type(2)));
                         const us2 sum = __builtin_bit_cast(us2, pc[t]) +
                                         __builtin_bit_cast(us2, (uint32_t)ia);
-                        in = (__builtin_bit_cast(uint32_t, sum) & 0xfff0fff0u) == 0u;
+                        in = (__builtin_bit_cast(uint32_t, sum) & tmask) == 0u;
                     } else {
                         in = (unsigned)(ia + ci[t]) < (unsigned)th &&
                              (unsigned)(jb + cj[t]) < (unsigned)tw;
@@ -848,7 +857,7 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
     // finalize: one node per lane, four passes over the tile
     const int kcap = a.max_pts;
     const unsigned long long imask = (1ull << kb) - 1ull;
-    for (int q0 = 0; q0 < kNodes; q0 += 64) {
+    for (int q0 = 0; q0 < kTW * TH; q0 += 64) {
         const int qq = q0 + lane;
         const int la = qq / kTW, lb = qq - la * kTW;
         const int q = la * kRS + lb;

@@ -83,12 +83,12 @@ def test_batch_plan_on_host():
     # at least the binned records of every item
     assert nbytes.value > 201_000 * 40
     s, a = ctypes.c_int32(), ctypes.c_int32()
-    assert lib.auv_batch_item_plan(h, 0, ctypes.byref(s), ctypes.byref(a)) == ag.AUV_OK
+    assert lib.auv_batch_item_plan(h, 0, ctypes.byref(s), ctypes.byref(a), None, None) == ag.AUV_OK
     # ~1150 soundings per disk with k = 16: the dense form by default
     assert (s.value, a.value) == (19, ag.AUV_ALGO_DENSE)
-    assert lib.auv_batch_item_plan(h, 1, ctypes.byref(s), ctypes.byref(a)) == ag.AUV_OK
+    assert lib.auv_batch_item_plan(h, 1, ctypes.byref(s), ctypes.byref(a), None, None) == ag.AUV_OK
     assert (s.value, a.value) == (19, ag.AUV_ALGO_SPARSE)
-    assert lib.auv_batch_item_plan(h, 3, ctypes.byref(s), ctypes.byref(a)) == ag.AUV_ERR_INVALID
+    assert lib.auv_batch_item_plan(h, 3, ctypes.byref(s), ctypes.byref(a), None, None) == ag.AUV_ERR_INVALID
     lib.auv_batch_destroy(h)
 
 
@@ -105,8 +105,19 @@ def test_batch_plan_reads_tune_table(tmp_path):
     h = ctypes.c_void_p()
     assert lib.auv_batch_plan(arr, 1, str(table).encode(), ctypes.byref(h)) == ag.AUV_OK
     s, a = ctypes.c_int32(), ctypes.c_int32()
-    assert lib.auv_batch_item_plan(h, 0, ctypes.byref(s), ctypes.byref(a)) == ag.AUV_OK
+    assert lib.auv_batch_item_plan(h, 0, ctypes.byref(s), ctypes.byref(a), None, None) == ag.AUV_OK
     assert (s.value, a.value) == (17, ag.AUV_ALGO_SPARSE)
+    tw, th = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.auv_batch_item_plan(h, 0, None, None, ctypes.byref(tw),
+                                   ctypes.byref(th)) == ag.AUV_OK
+    assert (tw.value, th.value) == (16, 16)  # no tile fields: the form's default
+    lib.auv_batch_destroy(h)
+    # a table with a node tile
+    table.write_text(f"class {dens} 6 bin_log2 16 algo {ag.AUV_ALGO_DENSE} tile 16 4 ms 0.1\n")
+    assert lib.auv_batch_plan(arr, 1, str(table).encode(), ctypes.byref(h)) == ag.AUV_OK
+    assert lib.auv_batch_item_plan(h, 0, ctypes.byref(s), ctypes.byref(a), ctypes.byref(tw),
+                                   ctypes.byref(th)) == ag.AUV_OK
+    assert (s.value, a.value, tw.value, th.value) == (16, ag.AUV_ALGO_DENSE, 16, 4)
     lib.auv_batch_destroy(h)
 
 

@@ -173,13 +173,18 @@ def test_batch_autotune_round_trip(ag, orc, tmp_path):
     assert rows, "autotune wrote no class"
     table = {}
     for r in rows:
-        assert r[3] == "bin_log2" and r[5] == "algo" and r[7] == "ms"
+        assert r[3] == "bin_log2" and r[5] == "algo" and r[7] == "tile" and r[10] == "ms"
         assert 12 <= int(r[4]) <= 26 and int(r[6]) in (ag.AUV_ALGO_SPARSE, ag.AUV_ALGO_DENSE)
-        assert float(r[8]) > 0.0
-        table[(int(r[1]), int(r[2]))] = (int(r[4]), int(r[6]))
+        tw, th = int(r[8]), int(r[9])
+        if int(r[6]) == ag.AUV_ALGO_DENSE:
+            assert tw * th == 64 and tw in (4, 8, 16)
+        else:
+            assert tw == 16 and th in (8, 16)
+        assert float(r[11]) > 0.0
+        table[(int(r[1]), int(r[2]))] = (int(r[4]), int(r[6]), tw, th)
     b0.close()
     b = ag.Batch([it.item for it in items], tune_path=path)
-    chosen = {b.item_plan(i) for i in range(len(items))}
+    chosen = {b.item_plan_full(i) for i in range(len(items))}
     assert chosen <= set(table.values())
     for it in items:
         it.clear()
@@ -187,6 +192,49 @@ def test_batch_autotune_round_trip(ag, orc, tmp_path):
     torch.cuda.synchronize()
     for k, it in enumerate(items):
         _check_item(orc, it, it.host(), f"tuned item {k} (plan {b.item_plan(k)})")
+    b.close()
+
+
+def _class_of(s):
+    """The batch's item class: floor(log2(expected soundings per disk + 1)),
+    round(log2(largest grid side))."""
+    g, r = s.grid, s.radius
+    area = (g.nx * g.dx + 2 * r) * (g.ny * g.dy + 2 * r)
+    pop = len(s.x) / area * np.pi * r * r
+    return int(np.floor(np.log2(pop + 1.0))), int(round(np.log2(max(g.nx, g.ny))))
+
+
+def test_batch_non_default_tiles(ag, orc, tmp_path):
+    """Every item planned with a node tile other than its form's default (from
+    a written tune table: window form 16 x 8, dense form 16 x 4 or 4 x 16),
+    run by the persistent kernels, against the oracle node by node."""
+    tiles = workload_cfg3_tiles(n_tiles=12, seed=5, scale=0.08, sides=(64, 128, 256))
+    items = [_Item(ag, s) for s in tiles]
+    b0 = ag.Batch([it.item for it in items])
+    lines, seen, dense_w = [], set(), 16
+    for k, it in enumerate(items):
+        key = _class_of(it.s)
+        if key in seen:
+            continue
+        seen.add(key)
+        s_log2, algo = b0.item_plan(k)
+        if algo == ag.AUV_ALGO_DENSE:
+            tw, th = dense_w, 64 // dense_w
+            dense_w = 4 if dense_w == 16 else 16
+        else:
+            tw, th = 16, 8
+        lines.append(f"class {key[0]} {key[1]} bin_log2 {s_log2} algo {algo} tile {tw} {th} ms 1")
+    b0.close()
+    path = tmp_path / "tune.txt"
+    path.write_text("\n".join(lines) + "\n")
+    b = ag.Batch([it.item for it in items], tune_path=str(path))
+    plans = [b.item_plan_full(i) for i in range(len(items))]
+    assert all((p[2], p[3]) in ((16, 8), (16, 4), (4, 16)) for p in plans), plans
+    assert {(p[2], p[3]) for p in plans} >= {(16, 8)}
+    b.launch()
+    torch.cuda.synchronize()
+    for k, it in enumerate(items):
+        _check_item(orc, it, it.host(), f"item {k} (plan {plans[k]})")
     b.close()
 
 
