@@ -82,8 +82,11 @@ def _load():
         lib.orc_bilinear.argtypes = [P(_Grid), vp, P(_Grid), vp, i32]
         lib.orc_bicubic.argtypes = [P(_Grid), vp, P(_Grid), vp, i32]
         lib.orc_kriging.argtypes = [P(_Grid), vp, P(_Grid), d, vp, i32]
+        lib.orc_variogram.argtypes = [P(_Grid), vp, i32, vp, vp, vp, vp]
+        lib.orc_fit_exponential.argtypes = [vp, vp, vp, i32, P(d), P(d)]
         for f in (lib.orc_bin_dims, lib.orc_bin, lib.orc_idw, lib.orc_idw_bounds, lib.orc_nearest,
-                  lib.orc_bilinear, lib.orc_bicubic, lib.orc_kriging):
+                  lib.orc_bilinear, lib.orc_bicubic, lib.orc_kriging, lib.orc_variogram,
+                  lib.orc_fit_exponential):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -240,3 +243,42 @@ def kriging(src_grid: Grid, src, dst_grid: Grid, range_m: float, nthreads: int =
     _check(lib.orc_kriging(ctypes.byref(src_grid.c()), _ptr(s), ctypes.byref(dst_grid.c()),
                            float(range_m), _ptr(d), nthreads), "orc_kriging")
     return d.reshape(dst_grid.ny, dst_grid.nx)
+
+
+def variogram(grid: Grid, src, nlags: int):
+    """O7: empirical semivariogram along the axes; returns (gamma_x, gamma_y,
+    pairs_x, pairs_y) for lags 1..nlags (lag k is k dx along x, k dy along y)."""
+    lib = _load()
+    s = _f64(src).reshape(-1)
+    if s.shape[0] != grid.nx * grid.ny:
+        raise ValueError("source size does not match its grid")
+    gx = np.empty(nlags, dtype=np.float64)
+    gy = np.empty(nlags, dtype=np.float64)
+    px = np.empty(nlags, dtype=np.int64)
+    py = np.empty(nlags, dtype=np.int64)
+    _check(lib.orc_variogram(ctypes.byref(grid.c()), _ptr(s), int(nlags), _ptr(gx), _ptr(gy),
+                             _ptr(px), _ptr(py)), "orc_variogram")
+    return gx, gy, px, py
+
+
+def fit_exponential(h, gamma, w):
+    """O8: weighted least-squares exponential variogram fit; returns
+    (range, sill, status) with status ORC_ERANGE (-2) when no sill was found
+    inside the scanned interval."""
+    lib = _load()
+    h, g, w = _f64(h), _f64(gamma), _f64(w)
+    a, c = ctypes.c_double(), ctypes.c_double()
+    rc = lib.orc_fit_exponential(_ptr(h), _ptr(g), _ptr(w), int(h.shape[0]), ctypes.byref(a),
+                                 ctypes.byref(c))
+    if rc not in (0, -2):
+        _check(rc, "orc_fit_exponential")
+    return a.value, c.value, rc
+
+
+def fit_grid_range(grid: Grid, src, nlags: int):
+    """O7 then O8 on both axes, weighted by pair counts: (range, sill, status)."""
+    gx, gy, px, py = variogram(grid, src, nlags)
+    k = np.arange(1, nlags + 1, dtype=np.float64)
+    h = np.concatenate([k * grid.dx, k * grid.dy])
+    return fit_exponential(h, np.concatenate([gx, gy]),
+                           np.concatenate([px, py]).astype(np.float64))

@@ -770,3 +770,125 @@ int orc_kriging(const orc_grid *sg, const double *src, const orc_grid *dg, doubl
     }
     return ORC_OK;
 }
+
+/* -------------------------------------------------------------- variogram -- */
+
+/* O7: empirical semivariogram along the grid axes (the classical method-of-
+ * moments estimator): for lag k = 1..nlags, the pairs (row a, column b) and
+ * (a, b + k) with both values finite give
+ *     gamma_x[k-1] = sum (z1 - z2)^2 / (2 * pairs_x[k-1])   (lag k * dx),
+ * the pairs (a, b) and (a + k, b) likewise gamma_y (lag k * dy); NaN where a
+ * lag has no pair.  The paper leaves the variogram's parameters unstated
+ * (Sec. III-C); this is the data the fit below reads. */
+int orc_variogram(const orc_grid *g, const double *src, int32_t nlags, double *gamma_x,
+                  double *gamma_y, int64_t *pairs_x, int64_t *pairs_y)
+{
+    if (!orc_grid_ok(g) || nlags < 1)
+        return ORC_EINVAL;
+    for (int32_t k = 1; k <= nlags; ++k) {
+        double sx = 0.0, sy = 0.0;
+        int64_t cx = 0, cy = 0;
+        for (int64_t a = 0; a < g->ny; ++a) {
+            for (int64_t b = 0; b < g->nx; ++b) {
+                const double z1 = src[a * g->nx + b];
+                if (!isfinite(z1))
+                    continue;
+                if (b + k < g->nx) {
+                    const double z2 = src[a * g->nx + b + k];
+                    if (isfinite(z2)) {
+                        sx += (z1 - z2) * (z1 - z2);
+                        cx += 1;
+                    }
+                }
+                if (a + k < g->ny) {
+                    const double z2 = src[(a + k) * g->nx + b];
+                    if (isfinite(z2)) {
+                        sy += (z1 - z2) * (z1 - z2);
+                        cy += 1;
+                    }
+                }
+            }
+        }
+        gamma_x[k - 1] = cx > 0 ? sx / (2.0 * (double)cx) : NAN;
+        gamma_y[k - 1] = cy > 0 ? sy / (2.0 * (double)cy) : NAN;
+        if (pairs_x)
+            pairs_x[k - 1] = cx;
+        if (pairs_y)
+            pairs_y[k - 1] = cy;
+    }
+    return ORC_OK;
+}
+
+/* Weighted residual of the exponential model at range a, with the sill at its
+ * least-squares value for that range (the model is linear in the sill). */
+static double orc_exp_residual(const double *h, const double *gam, const double *w, int32_t n,
+                               double a, double *sill)
+{
+    double sgf = 0.0, sff = 0.0, sgg = 0.0;
+    for (int32_t j = 0; j < n; ++j) {
+        if (!(w[j] > 0.0) || !isfinite(gam[j]))
+            continue;
+        const double f = 1.0 - exp(-h[j] / a);
+        sgf += w[j] * gam[j] * f;
+        sff += w[j] * f * f;
+        sgg += w[j] * gam[j] * gam[j];
+    }
+    const double c = sff > 0.0 ? sgf / sff : 0.0;
+    if (sill)
+        *sill = c;
+    return sgg - 2.0 * c * sgf + c * c * sff;
+}
+
+/* O8: weighted least-squares fit of gamma(h) = C0 (1 - exp(-h / a)) to n
+ * points (h_j > 0 in metres, gamma_j, weights w_j >= 0; points with zero
+ * weight or a non-finite gamma are ignored): the range a minimises the
+ * residual with C0 at its least-squares value for that a.  a is searched on a
+ * log grid of 20001 values from min(h) / 100 to 1000 max(h), then refined by
+ * ternary search between the grid neighbours of the best value.  Returns
+ * ORC_EINVAL for no usable point, ORC_ERANGE when the best range is an end of
+ * the grid (no sill within it). */
+int orc_fit_exponential(const double *h, const double *gam, const double *w, int32_t n,
+                        double *range, double *sill)
+{
+    double hmin = INFINITY, hmax = 0.0;
+    int32_t used = 0;
+    for (int32_t j = 0; j < n; ++j) {
+        if (!(w[j] > 0.0) || !isfinite(gam[j]) || !(h[j] > 0.0))
+            continue;
+        hmin = fmin(hmin, h[j]);
+        hmax = fmax(hmax, h[j]);
+        ++used;
+    }
+    if (used < 2)
+        return ORC_EINVAL;
+    const int32_t m = 20001;
+    const double l0 = log(hmin / 100.0), l1 = log(1000.0 * hmax);
+    int32_t best = 0;
+    double best_r = INFINITY;
+    for (int32_t i = 0; i < m; ++i) {
+        const double a = exp(l0 + (l1 - l0) * (double)i / (double)(m - 1));
+        const double r = orc_exp_residual(h, gam, w, n, a, NULL);
+        if (r < best_r) {
+            best_r = r;
+            best = i;
+        }
+    }
+    if (best == 0 || best == m - 1) {
+        *range = exp(best == 0 ? l0 : l1);
+        orc_exp_residual(h, gam, w, n, *range, sill);
+        return ORC_ERANGE;
+    }
+    double lo = l0 + (l1 - l0) * (double)(best - 1) / (double)(m - 1);
+    double hi = l0 + (l1 - l0) * (double)(best + 1) / (double)(m - 1);
+    for (int it = 0; it < 200; ++it) {
+        const double p = lo + (hi - lo) / 3.0, q = hi - (hi - lo) / 3.0;
+        if (orc_exp_residual(h, gam, w, n, exp(p), NULL) <=
+            orc_exp_residual(h, gam, w, n, exp(q), NULL))
+            hi = q;
+        else
+            lo = p;
+    }
+    *range = exp(0.5 * (lo + hi));
+    orc_exp_residual(h, gam, w, n, *range, sill);
+    return ORC_OK;
+}

@@ -107,6 +107,24 @@ int orc_bicubic(const orc_grid *src_g, const double *src, const orc_grid *dst_g,
 int orc_kriging(const orc_grid *src_g, const double *src, const orc_grid *dst_g,
                 double range, double *dst, int32_t nthreads);
 
+/* O7: empirical semivariogram along the grid axes (classical estimator):
+ * gamma_x[k-1] over the pairs (a, b), (a, b + k) with both values finite,
+ * gamma_y[k-1] over (a, b), (a + k, b), each sum of squared differences over
+ * twice the pair count (NaN without pairs), k = 1..nlags; pair counts to
+ * pairs_x / pairs_y when non-null.  The variogram whose parameters Sec. III-C
+ * leaves unstated is fitted to these. */
+int orc_variogram(const orc_grid *g, const double *src, int32_t nlags, double *gamma_x,
+                  double *gamma_y, int64_t *pairs_x, int64_t *pairs_y);
+
+/* O8: weighted least-squares fit of the exponential variogram
+ * gamma(h) = C0 (1 - exp(-h / a)) (Sec. III-C's model) to n points (h_j > 0,
+ * gamma_j, w_j >= 0; zero-weight or non-finite points ignored): a by a log-grid
+ * scan and ternary refinement of the residual with C0 at its least-squares
+ * value.  ORC_ERANGE when the best range is an end of the scanned interval
+ * [min h / 100, 1000 max h] (no sill). */
+int orc_fit_exponential(const double *h, const double *gam, const double *w, int32_t n,
+                        double *range, double *sill);
+
 #ifdef __cplusplus
 }
 #endif
