@@ -271,8 +271,9 @@ def grid_b_report(ag, dev, with_cpu, n_fine=2048):
     base = grid_b_case(n_fine, 0.0)
     out = {"workload": f"{n_fine}^2 fractal seafloor at 4 m, every other node recorded, "
                        "random removal of recorded nodes; fills: bilinear, Catmull-Rom, "
-                       "kriging (range 24 m) from the recorded grid, IDW p=2 r=12 m from "
-                       "the recorded nodes", "cases": []}
+                       "kriging (range 24 m, and the range fitted to the recorded grid's "
+                       "semivariogram) from the recorded grid, IDW p=2 r=12 m from the "
+                       "recorded nodes", "cases": []}
     for frac in (0.01, 0.05, 0.1):
         c = grid_b_case(n_fine, frac, truth=base["truth"])
         cs, ts = c["coarse_spec"], c["truth_spec"]
@@ -290,14 +291,27 @@ def grid_b_report(ag, dev, with_cpu, n_fine=2048):
             bins = ag.auv_bin_points(grid, x, y, z, radius, 0, ws=ws, stream=stream)
             ag.auv_interp_idw(grid, bins, params, fine, None, None, None, stream=stream)
 
+        # the kriging range fitted to the recorded grid: its semivariogram
+        # along the axes at lags 1..16 (8..128 m), exponential model
+        t0 = time.perf_counter()
+        fit_range, fit_sill, fit_rc = ag.fit_variogram_range(coarse, cs, 64, stream=stream)
+        fit_ms = (time.perf_counter() - t0) * 1e3
+        if fit_rc != ag.AUV_OK:
+            fit_range = rm
         fns = {
             "bilinear": lambda: ag.auv_resample_bilinear(coarse, cs, fine, ts, stream=stream),
             "bicubic": lambda: ag.auv_resample_bicubic(coarse, cs, fine, ts, stream=stream),
             "kriging": lambda: ag.auv_resample_kriging(coarse, cs, fine, ts, rm, stream=stream),
+            "kriging_fitted": lambda: ag.auv_resample_kriging(coarse, cs, fine, ts, fit_range,
+                                                              stream=stream),
             "idw": idw,
         }
         case = {"removal": frac, "recorded": int(x.numel()),
-                "interpolated": int(c["interp"].sum()), "methods": {}}
+                "interpolated": int(c["interp"].sum()),
+                "variogram_fit": {"range_m": round(fit_range, 3), "sill_m2": round(fit_sill, 3),
+                                  "status": int(fit_rc), "lags": 64,
+                                  "host_ms_incl_gpu": round(fit_ms, 3)},
+                "methods": {}}
         for m, fn in fns.items():
             ms = _median_ms(fn, stream, 20)
             fn()

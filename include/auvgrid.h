@@ -231,6 +231,35 @@ auv_status auv_resample_kriging(const float *src, const auv_grid_desc *s,
                                 float *dst, const auv_grid_desc *d, double range,
                                 auv_stream stream);
 
+/* Empirical semivariogram of a grid along its axes, the data the kriging
+ * variogram's range is fitted to (Sec. III-C gives the exponential model but
+ * not its parameters).  For lag k = 1..nlags: gamma_x[k-1] = the sum of
+ * (z1 - z2)^2 over the pairs (row a, column b), (a, b + k) with both values
+ * finite, over twice their count pairs_x[k-1] (lag k * dx metres); gamma_y
+ * likewise over (a, b), (a + k, b) (lag k * dy); NaN where a lag has no pair.
+ *   src    device float [s.ny][s.nx];
+ *   ws     device workspace of auv_variogram_workspace_size bytes, 256-B aligned;
+ *   gamma_x, gamma_y  host double [nlags];  pairs_x, pairs_y  host int64 [nlags],
+ *          nullable.
+ * Sums run in FP64 in a fixed order (deterministic).  Synchronises `stream`.
+ * Errors: AUV_ERR_INVALID for nlags outside [1, 1024] or a bad descriptor,
+ * AUV_ERR_BUDGET for a short workspace. */
+auv_status auv_variogram_workspace_size(const auv_grid_desc *s, int32_t nlags, size_t *bytes);
+auv_status auv_variogram(const float *src, const auv_grid_desc *s, int32_t nlags, void *ws,
+                         size_t ws_bytes, double *gamma_x, double *gamma_y, int64_t *pairs_x,
+                         int64_t *pairs_y, auv_stream stream);
+
+/* Weighted least-squares fit of the exponential variogram of Sec. III-C,
+ * gamma(h) = sill (1 - exp(-h / range)), to n host points (h_j > 0 metres,
+ * gamma_j, weights w_j >= 0, e.g. pair counts; points with zero weight or a
+ * non-finite gamma are ignored): the sill at its least-squares value for each
+ * range, the range searched on a log scale over [min h / 100, 1000 max h] and
+ * refined by golden section.  Host arithmetic only.  Errors: AUV_ERR_INVALID
+ * for fewer than two usable points; AUV_ERR_RANGE when the best range is an
+ * end of that interval (no sill: *range and *sill still hold the end). */
+auv_status auv_fit_exponential(const double *h, const double *gamma, const double *w, int32_t n,
+                               double *range, double *sill);
+
 /* ------------------------------------------------- no device allocation --
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.

@@ -109,6 +109,11 @@ def load_library(path: str = LIB_PATH):
         "auv_bins_destroy": ([vp], None),
         "auv_interp_idw": ([vp, vp, P(auv_idw_params), vp, vp, vp, vp, vp], ctypes.c_int),
         "auv_interp_nearest": ([vp, vp, d, vp, vp, vp], ctypes.c_int),
+        "auv_variogram_workspace_size": ([P(auv_grid_desc), i32, P(ctypes.c_size_t)],
+                                         ctypes.c_int),
+        "auv_variogram": ([vp, P(auv_grid_desc), i32, vp, ctypes.c_size_t, vp, vp, vp, vp, vp],
+                          ctypes.c_int),
+        "auv_fit_exponential": ([vp, vp, vp, i32, P(d), P(d)], ctypes.c_int),
         "auv_grid_idw_noalloc": ([vp, vp, vp, vp, i64, i32, P(auv_idw_params), vp, vp, vp, vp,
                                   vp], ctypes.c_int),
         "auv_resample_bilinear": ([vp, P(auv_grid_desc), vp, P(auv_grid_desc), vp],
@@ -327,6 +332,52 @@ def auv_grid_idw_noalloc(grid: Grid, x: torch.Tensor, y: torch.Tensor, z: torch.
 
 
 AUV_NOALLOC_SCRATCH_BYTES = 160 << 20
+
+
+def auv_variogram(src: torch.Tensor, s_desc, nlags: int, stream=None):
+    """Empirical semivariogram along the axes: (gamma_x, gamma_y, pairs_x,
+    pairs_y) as numpy arrays for lags 1..nlags (workspace allocated here)."""
+    import numpy as np
+    lib = load_library()
+    if not isinstance(s_desc, auv_grid_desc):
+        s_desc = make_desc(s_desc.x0, s_desc.y0, s_desc.dx, s_desc.dy, s_desc.nx, s_desc.ny)
+    nb = ctypes.c_size_t()
+    _check(lib.auv_variogram_workspace_size(ctypes.byref(s_desc), int(nlags), ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=src.device)
+    gx = np.empty(nlags, dtype=np.float64)
+    gy = np.empty(nlags, dtype=np.float64)
+    px = np.empty(nlags, dtype=np.int64)
+    py = np.empty(nlags, dtype=np.int64)
+    _check(lib.auv_variogram(_dev(src, torch.float32, "src", s_desc.nx * s_desc.ny),
+                             ctypes.byref(s_desc), int(nlags), ctypes.c_void_p(ws.data_ptr()),
+                             nb.value, gx.ctypes.data, gy.ctypes.data, px.ctypes.data,
+                             py.ctypes.data, _stream(stream)))
+    return gx, gy, px, py
+
+
+def auv_fit_exponential(h, gamma, w):
+    """Exponential variogram fit: (range, sill, status); status AUV_ERR_RANGE
+    when no sill lies inside the searched interval."""
+    import numpy as np
+    lib = load_library()
+    h, g, w = (np.ascontiguousarray(v, dtype=np.float64) for v in (h, gamma, w))
+    a, c = ctypes.c_double(), ctypes.c_double()
+    rc = lib.auv_fit_exponential(h.ctypes.data, g.ctypes.data, w.ctypes.data, int(h.shape[0]),
+                                 ctypes.byref(a), ctypes.byref(c))
+    if rc not in (AUV_OK, AUV_ERR_RANGE):
+        _check(rc)
+    return a.value, c.value, rc
+
+
+def fit_variogram_range(src: torch.Tensor, s_desc, nlags: int, stream=None):
+    """auv_variogram on both axes, then auv_fit_exponential weighted by the
+    pair counts: (range, sill, status)."""
+    import numpy as np
+    gx, gy, px, py = auv_variogram(src, s_desc, nlags, stream)
+    k = np.arange(1, nlags + 1, dtype=np.float64)
+    h = np.concatenate([k * s_desc.dx, k * s_desc.dy])
+    return auv_fit_exponential(h, np.concatenate([gx, gy]),
+                               np.concatenate([px, py]).astype(np.float64))
 
 
 def auv_interp_nearest(grid: Grid, bins: Bins, radius: float, idx_out: torch.Tensor,
