@@ -408,7 +408,7 @@ def precision_report(ag, dev):
     return out
 
 
-def batched_report(ag, dev, reps=20):
+def batched_report(ag, dev, reps=20, with_plain=True):
     """256 uneven tiles (1e3..2e5 soundings, 64^2..1024^2 nodes, p in {1,2,3}):
     the plain form (tile after tile, default bin size and kernel choice, no
     graph) against the batched form (autotuned per tile class, batched
@@ -460,7 +460,7 @@ def batched_report(ag, dev, reps=20):
         ms = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
         return float(np.median(ms)), float(ms.min())
 
-    plain_med, plain_min = timed(plain.launch_plain)
+    plain_med, plain_min = timed(plain.launch_plain) if with_plain else (float("nan"),) * 2
     batch_med, batch_min = timed(tuned.launch)
     # selected pairs of every tile (per-item IDW with counts, after timing)
     pairs = {"dense": 0, "sparse": 0}
@@ -481,10 +481,11 @@ def batched_report(ag, dev, reps=20):
                     "{64..1024} @ 2 m, p in {1,2,3}, r=6 m, k=16, min 1; IDW + nearest",
         "soundings": int(n_pts), "nodes": int(n_nodes),
         "input_sha": checksum(*[a for s in tiles for a in (s.x, s.y, s.z)]),
-        "plain_ms": round(plain_med, 4), "plain_min_ms": round(plain_min, 4),
+        "plain_ms": round(plain_med, 4) if with_plain else None,
+        "plain_min_ms": round(plain_min, 4) if with_plain else None,
         "batched_ms": round(batch_med, 4), "batched_min_ms": round(batch_min, 4),
-        "speedup": round(plain_med / batch_med, 3),
-        "plain_nodes_per_s": round(n_nodes / (plain_med * 1e-3), 1),
+        "speedup": round(plain_med / batch_med, 3) if with_plain else None,
+        "plain_nodes_per_s": round(n_nodes / (plain_med * 1e-3), 1) if with_plain else None,
         "batched_nodes_per_s": round(n_nodes / (batch_med * 1e-3), 1),
         "batched_hbm_frac": round(alg_bytes / (batch_med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "selected_pairs": pairs,
@@ -599,6 +600,8 @@ def main():
                     help="skip the UTM-scale precision-variant error report")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 256-tile plain-vs-batched comparison")
+    ap.add_argument("--no-plain-batch", action="store_true",
+                    help="batched report without the plain item-by-item comparison")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the 16-vehicle serving replay (FIFO vs continuous batching)")
     ap.add_argument("--serving-seconds", type=float, default=60.0,
@@ -818,7 +821,7 @@ def main():
 
     batched = None
     if not args.no_batched:
-        batched = batched_report(ag, dev)
+        batched = batched_report(ag, dev, with_plain=not args.no_plain_batch)
 
     serving = None
     if not args.no_serving:
