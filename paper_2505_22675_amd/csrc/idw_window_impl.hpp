@@ -721,13 +721,10 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
             lds_v4i *rp0 = (lds_v4i *)sm.r0;
             asm volatile("" : "+v"(rp0));
             const float4 *rpv = sm.rv;
-            while (m) {
-                const int l = __ffsll((long long)m) - 1;
-                m &= m - 1ull;
+            // Visit of the kept sounding in lane l, whose record is (v0, v1).
+            auto visit = [&](int l, const v4i &v0, const v4i &v1) {
                 const int sx = sext23(__builtin_amdgcn_readlane(px, l));
                 const int sy = sext23(__builtin_amdgcn_readlane(py, l));
-                const v4i v0 = rp0[0], v1 = rp0[1];
-                rp0 += 2;
                 const int4 w0 = make_int4(v0.x, v0.y, v0.z, v0.w);
                 const int4 w1 = make_int4(v1.x, v1.y, v1.z, v1.w);
                 const int ia = w0.x, jb = w0.y, qb8 = w0.z, qb4 = w0.w;
@@ -843,6 +840,30 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                         }
                     }
                 }
+            };
+            // The next record is read while the current one is applied (two
+            // register sets, so the prefetch needs no copies); the records
+            // were written before the wave barrier above.
+            v4i a0 = rp0[0], a1 = rp0[1], b0, b1;
+            while (m) {
+                int l = __ffsll((long long)m) - 1;
+                m &= m - 1ull;
+                if (m) {
+                    b0 = rp0[2];
+                    b1 = rp0[3];
+                }
+                visit(l, a0, a1);
+                rp0 += 2;
+                if (!m)
+                    break;
+                l = __ffsll((long long)m) - 1;
+                m &= m - 1ull;
+                if (m) {
+                    a0 = rp0[2];
+                    a1 = rp0[3];
+                }
+                visit(l, b0, b1);
+                rp0 += 2;
             }
         }
     }
