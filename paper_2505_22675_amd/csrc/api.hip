@@ -2,6 +2,7 @@
 // kernel launches.  Every entry point validates synchronously and only
 // enqueues device work on the caller's stream.
 #include "auv_internal.hpp"
+#include "idw_dense_impl.hpp"
 
 #include <cmath>
 #include <cstring>
@@ -301,10 +302,12 @@ auv_status auv_interp_idw(const auv_grid *grid, const auv_bins *bins,
         const double area = (grid->d.nx * grid->d.dx + 2 * r) * (grid->d.ny * grid->d.dy + 2 * r);
         const double lambda = (double)bins->n / area * 3.141592653589793 * r * r;
         const bool dense_ok = params->max_pts >= 1 && params->max_pts <= 32 &&
-                              params->precision == AUV_P_FP32_REBASE;
+                              params->precision == AUV_P_FP32_REBASE &&
+                              dense::dense_key_ok(a.R, bins->v.idx_bits);
         if (params->algo == AUV_ALGO_DENSE && !dense_ok)
             return fail(AUV_ERR_INVALID,
-                        "the dense form needs 1 <= max_pts <= 32 and AUV_P_FP32_REBASE");
+                        "the dense form needs 1 <= max_pts <= 32, AUV_P_FP32_REBASE and "
+                        "(R^2 << index bits) below 2^62");
         a.dense = params->algo == AUV_ALGO_DENSE ||
                   (params->algo == AUV_ALGO_AUTO && dense_ok && lambda >= 0.5 * params->max_pts);
         a.span = params->algo == AUV_ALGO_SPAN;

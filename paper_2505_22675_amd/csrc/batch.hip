@@ -224,8 +224,13 @@ ClassKey class_of(const auv_batch_item &it)
 
 bool dense_allowed(const auv_batch_item &it)
 {
+    int bits = 1;
+    while (bits < 31 && (int64_t(1) << bits) < it.n)
+        ++bits;
+    const double Rd = std::rint(it.params.radius * kLatticePerMetre);
     return it.params.max_pts >= 1 && it.params.max_pts <= 32 &&
-           it.params.precision == AUV_P_FP32_REBASE;
+           it.params.precision == AUV_P_FP32_REBASE && Rd < 2147483648.0 &&
+           dense::dense_key_ok((int32_t)Rd, bits);
 }
 
 struct Choice {
@@ -442,7 +447,8 @@ bool make_idw_item(const auv_batch_item &it, const auv_bin_view &bv, const IdwAr
     d.span = 0;
     bool ok = true;
     if (d.dense) {
-        ok = it.params.max_pts >= 1 && it.params.max_pts <= kBatchDenseK;
+        ok = it.params.max_pts >= 1 && it.params.max_pts <= kBatchDenseK &&
+             dense::dense_key_ok(a.R, bv.idx_bits);
         const int tw = dense::dense_tile_w(a), th = 64 / tw;
         d.ntx = (it.grid.nx + tw - 1) / tw;
         d.ntiles = d.ntx * ((it.grid.ny + th - 1) / th);

@@ -25,6 +25,8 @@ auv_status launch_idw_dense(const auv_bin_view &bv, const IdwArgs &a, int pmode,
 {
     if (a.max_pts < 1 || a.max_pts > 32)
         return fail(AUV_ERR_INVALID, "the dense form needs 1 <= max_pts <= 32");
+    if (!dense_key_ok(a.R, bv.idx_bits))
+        return fail(AUV_ERR_RANGE, "the dense form needs (R^2 << index bits) below 2^62");
     const int TW = dense_tile_w(a), TH = 64 / TW;
     const int ntx = (a.nx + TW - 1) / TW, nty = (a.ny + TH - 1) / TH;
     switch (a.mode) {

@@ -28,6 +28,28 @@ __device__ inline int xcd_tile(int bid, int ntiles)
     return xcd * q + min(xcd, rem) + local;
 }
 
+// FP64 minimum / maximum of two non-NaN values (the list entries below):
+// one instruction each, without the NaN quieting the compiler adds to fmin /
+// fmax of values it cannot prove canonical.
+__device__ inline double dmin(double a, double b)
+{
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ inline double dmax(double a, double b)
+{
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// Key held in an FP64 list entry (see dense_node).
+__device__ inline unsigned long long key_of(double v)
+{
+    return (unsigned long long)__double_as_longlong(v) - (1ull << 52);
+}
+
 struct NodeL {
     int X, q;
 };
@@ -67,6 +89,12 @@ template <int kMode, int KMAX>
 __device__ void dense_node(const auv_bin_view &bv, const IdwArgs &a, int b, int an, int pmode)
 {
     constexpr bool kIdw = (kMode & 1) != 0;
+    // explicitly global pointers (descriptors read from memory would
+    // otherwise give flat loads)
+    const auto gX = gmem(bv.X), gY = gmem(bv.Y), gI = gmem(bv.idx);
+    const auto gC = gmem(bv.cell_start);
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const auto gR = gmem(reinterpret_cast<const v4i *>(bv.rec));
     const NodeL nx_l = node_lat(b, a.dx), ny_l = node_lat(an, a.dy);
     const int Xn = nx_l.X, Yn = ny_l.X;
     const int s = bv.bin_log2;
@@ -81,83 +109,110 @@ __device__ void dense_node(const auv_bin_view &bv, const IdwArgs &a, int b, int 
     const int ux = Xn + hB - (bxn << s), uy = Yn + hB - (byn << s);
     const int m0 = min(min(ux, B - ux), min(uy, B - uy));
 
-    unsigned long long list[KMAX];
+    // The k smallest keys, ascending.  A key (below 2^62) is held as the
+    // FP64 number whose bit pattern is key + 2^52: a normal positive double,
+    // so FP64 order is key order and the sorted insert is a min/max network
+    // (list'[j] = max(list[j-1], min(key, list[j]))), two full-rate FP64
+    // operations per entry instead of compares and 64-bit selects.
+    double list[KMAX];
 #pragma unroll
     for (int j = 0; j < KMAX; ++j)
-        list[j] = ~0ull;
+        list[j] = __builtin_huge_val();
     int found = 0;
 
-    auto consider = [&](int k) {
-        const int dX = bv.X[k] - Xn, dY = bv.Y[k] - Yn;
+    auto consider = [&](int k, int Xk, int Yk) {
+        const int dX = Xk - Xn, dY = Yk - Yn;
         const long long D2 = (long long)dX * dX + (long long)dY * dY;
         if (D2 > R2)
             return;
         ++found;
-        const unsigned long long key = ((unsigned long long)D2 << kb) | (unsigned)bv.idx[k];
+        const unsigned long long key = ((unsigned long long)D2 << kb) | (unsigned)gI[k];
+        const double kd = __longlong_as_double((long long)(key + (1ull << 52)));
         // insert into the ascending list, dropping its largest entry
-        if (key < list[KMAX - 1]) {
+        if (kd < list[KMAX - 1]) {
 #pragma unroll
-            for (int j = KMAX - 1; j > 0; --j) {
-                const unsigned long long lo = list[j - 1], cur = list[j];
-                list[j] = key < lo ? lo : (key < cur ? key : cur);
-            }
-            list[0] = key < list[0] ? key : list[0];
+            for (int j = KMAX - 1; j > 0; --j)
+                list[j] = dmax(list[j - 1], dmin(kd, list[j]));
+            list[0] = dmin(kd, list[0]);
         }
     };
+    // the soundings of one bin segment, four at a time (their coordinates
+    // are loaded together, so the loads overlap)
     auto segment = [&](int row, int c0, int c1) {
         c0 = max(c0, 0);
         c1 = min(c1, bv.nbx - 1);
         if (row < 0 || row >= bv.nby || c0 > c1)
             return;
         const int id = row * bv.nbx;
-        const int e = bv.cell_start[id + c1 + 1];
-        for (int k = bv.cell_start[id + c0]; k < e; ++k)
-            consider(k);
+        const int e = gC[id + c1 + 1];
+        for (int k = gC[id + c0]; k < e; k += 4) {
+            int Xk[4], Yk[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                Xk[u] = k + u < e ? gX[k + u] : 0;
+                Yk[u] = k + u < e ? gY[k + u] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (k + u < e)
+                    consider(k + u, Xk[u], Yk[u]);
+        }
     };
 
     {
         for (int d = 0;; ++d) {
-            segment(byn - d, bxn - d, bxn + d);
-            if (d > 0) {
-                segment(byn + d, bxn - d, bxn + d);
-                for (int r = byn - d + 1; r <= byn + d - 1; ++r) {
-                    segment(r, bxn - d, bxn - d);
-                    segment(r, bxn + d, bxn + d);
+            // ring d: its top and bottom rows, then the left and right bins of
+            // the rows between (one loop, so the candidate code is inlined once)
+            const int nseg = d == 0 ? 1 : 4 * d;
+            for (int sg = 0; sg < nseg; ++sg) {
+                int row, c0, c1;
+                if (sg < 2) {
+                    row = sg == 0 ? byn - d : byn + d;
+                    c0 = bxn - d;
+                    c1 = bxn + d;
+                } else {
+                    row = byn - d + 1 + ((sg - 2) >> 1);
+                    c0 = c1 = (sg & 1) ? bxn + d : bxn - d;
                 }
+                segment(row, c0, c1);
             }
             // every unvisited sounding is at least lb away
             const long long lb = (long long)d * B + m0;
             if (lb * lb > R2)
                 break;
-            if (found >= kcap && (long long)(list[kcap - 1] >> kb) < lb * lb)
+            if (found >= kcap && (long long)(key_of(list[kcap - 1]) >> kb) < lb * lb)
                 break;
         }
     }
 
     const int m = min(found, kcap);
+    unsigned long long keys[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j)
+        keys[j] = key_of(list[j]);
     const int64_t o = (int64_t)an * a.nx + b;
     const unsigned long long imask = (1ull << kb) - 1ull;
     if (kMode & 2) {
-        const int bi = m > 0 ? (int)(list[0] & imask) : -1;
+        const int bi = m > 0 ? (int)(keys[0] & imask) : -1;
         if (a.nn_idx_out)
-            a.nn_idx_out[o] = bi;
+            gmem(a.nn_idx_out)[o] = bi;
         if (a.nn_z_out)
-            a.nn_z_out[o] = m > 0 ? __int_as_float(bv.rec[bi].w) : NAN;
+            gmem(a.nn_z_out)[o] = m > 0 ? __int_as_float(gR[bi].w) : NAN;
     }
     if constexpr (kIdw) {
         if (a.cnt_out)
-            a.cnt_out[o] = m;
+            gmem(a.cnt_out)[o] = m;
         float v;
         if (m == 0) {
             v = NAN;
-        } else if ((list[0] >> kb) == 0ull) {
+        } else if ((keys[0] >> kb) == 0ull) {
             // hits: the members with D^2 == 0, in ascending index
             double hs = 0.0;
             int nh = 0;
 #pragma unroll
             for (int j = 0; j < KMAX; ++j) {
-                if (j < m && (list[j] >> kb) == 0ull) {
-                    hs += (double)__int_as_float(bv.rec[(int)(list[j] & imask)].w);
+                if (j < m && (keys[j] >> kb) == 0ull) {
+                    hs += (double)__int_as_float(gR[(int)(keys[j] & imask)].w);
                     ++nh;
                 }
             }
@@ -165,12 +220,12 @@ __device__ void dense_node(const auv_bin_view &bv, const IdwArgs &a, int b, int 
         } else if (m < a.min_pts) {
             v = NAN;
         } else {
-            const float z0 = __int_as_float(bv.rec[(int)(list[0] & imask)].w);
+            const float z0 = __int_as_float(gR[(int)(keys[0] & imask)].w);
             float num = 0.0f, den = 0.0f, zmin = z0, zmax = z0;
 #pragma unroll
             for (int j = 0; j < KMAX; ++j) {
                 if (j < m) {
-                    const int4 r = bv.rec[(int)(list[j] & imask)];
+                    const v4i r = gR[(int)(keys[j] & imask)];
                     const float z = __int_as_float(r.w);
                     const int qx = (int)(int16_t)((uint32_t)r.z & 0xffffu);
                     const int qy = (int)(int16_t)((uint32_t)r.z >> 16);
@@ -187,8 +242,18 @@ __device__ void dense_node(const auv_bin_view &bv, const IdwArgs &a, int b, int 
             r = fmin(fmax(r, (double)zmin), (double)zmax);
             v = (float)r;
         }
-        a.z_out[o] = v;
+        gmem(a.z_out)[o] = v;
     }
+}
+
+// Whether the dense form's keys fit: (R^2 << index bits) plus the largest
+// index stays below 2^62 (the FP64 list entries hold key + 2^52).
+__host__ __device__ inline bool dense_key_ok(int32_t R, int32_t idx_bits)
+{
+    const unsigned __int128 top = ((unsigned __int128)((unsigned long long)R * (unsigned long long)R)
+                                   << idx_bits) +
+                                  ((unsigned __int128)1 << idx_bits);
+    return top < ((unsigned __int128)1 << 62);
 }
 
 // Node tile of the dense form: tile_w columns (a power of two from 1 to 64,

@@ -593,24 +593,28 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
         pc[t] = v ? ((uint32_t)ci[t] << 16) | (uint32_t)cj[t] : 0x40004000u;
     }
 
-    __syncthreads();  // the previous tile of this wave is finished with LDS
-    for (int q = lane; q < kAcc; q += 64) {
-        s_nd[q] = make_float2(0.0f, 0.0f);
-        s_cnt[q] = 0;
-        s_lo[q] = INFINITY;
-        s_hi[q] = -INFINITY;
-        if constexpr (kPacked) {
-            if constexpr (kKey)
-                s_key[q] = ~0ull;
-        } else {
-            s_bd2[q] = 1e300;
-            s_bidx[q] = INT_MAX;
-            s_bz[q] = 0.0f;
+
+    // accumulators cleared once the tile is known to have candidates
+    auto clear_acc = [&]() {
+        __syncthreads();  // the previous tile of this wave is finished with LDS
+        for (int q = lane; q < kAcc; q += 64) {
+            s_nd[q] = make_float2(0.0f, 0.0f);
+            s_cnt[q] = 0;
+            s_lo[q] = INFINITY;
+            s_hi[q] = -INFINITY;
+            if constexpr (kPacked) {
+                if constexpr (kKey)
+                    s_key[q] = ~0ull;
+            } else {
+                s_bd2[q] = 1e300;
+                s_bidx[q] = INT_MAX;
+                s_bz[q] = 0.0f;
+            }
+            if constexpr (kPmode == 0)
+                s_emax[q] = -INFINITY;
         }
-        if constexpr (kPmode == 0)
-            s_emax[q] = -INFINITY;
-    }
-    __syncthreads();
+        __syncthreads();
+    };
 
     // bins covering the tile grown by R
     const int hB = bv.halo << bv.bin_log2;
@@ -626,6 +630,8 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
     float zref = 0.0f;
     bool have_ref = false;
 
+    if (nrows <= 0)
+        clear_acc();
     for (int r0 = 0; r0 < nrows; r0 += kMaxRows) {
         const int nr = min(kMaxRows, nrows - r0);
         int beg = 0, len = 0;
@@ -642,6 +648,34 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                 inc += u;
         }
         const int total = __shfl(inc, 63, 64);
+        if (r0 == 0) {
+            if constexpr ((kMode & 4) == 0) {
+                if (total == 0 && nrows <= kMaxRows) {
+                    // no sounding can reach the tile: its outputs are empty
+                    const size_t tbase = (size_t)ta0 * a.nx + tb0;
+                    for (int q0 = 0; q0 < kTW * TH; q0 += 64) {
+                        const int qq = q0 + lane;
+                        const int la = qq / kTW, lb = qq - la * kTW;
+                        if (la < th && lb < tw) {
+                            const uint32_t ob = (uint32_t)(la * a.nx + lb) << 2;
+                            if (kMode & 2) {
+                                if (a.nn_idx_out)
+                                    *byte_at(a.nn_idx_out + tbase, ob) = -1;
+                                if (a.nn_z_out)
+                                    *byte_at(a.nn_z_out + tbase, ob) = NAN;
+                            }
+                            if constexpr (kIdw) {
+                                if (a.cnt_out)
+                                    *byte_at(a.cnt_out + tbase, ob) = 0;
+                                *byte_at(a.z_out + tbase, ob) = NAN;
+                            }
+                        }
+                    }
+                    return;
+                }
+            }
+            clear_acc();
+        }
         __syncthreads();
         if (lane < nr) {
             s_beg[lane] = beg;
@@ -878,26 +912,13 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
     // finalize: one node per lane, four passes over the tile
     const int kcap = a.max_pts;
     const unsigned long long imask = (1ull << kb) - 1ull;
-    for (int q0 = 0; q0 < kTW * TH; q0 += 64) {
-        const int qq = q0 + lane;
-        const int la = qq / kTW, lb = qq - la * kTW;
-        const int q = la * kRS + lb;
-        const bool act = la < th && lb < tw;
-        const int cnt = s_cnt[q];
-        int bi;
-        bool hit;
-        if constexpr (kKey) {
-            const unsigned long long key = s_key[q];
-            bi = (int)(key & imask);
-            hit = (key >> kb) == 0ull;
-        } else if constexpr (kPacked) {
-            bi = 0;
-            hit = false;
-        } else {
-            bi = s_bidx[q];
-            hit = s_bd2[q] == 0.0;
-        }
-        if constexpr ((kMode & 4) != 0) {
+    if constexpr ((kMode & 4) != 0) {
+        for (int q0 = 0; q0 < kTW * TH; q0 += 64) {
+            const int qq = q0 + lane;
+            const int la = qq / kTW, lb = qq - la * kTW;
+            const int q = la * kRS + lb;
+            const bool act = la < th && lb < tw;
+            const int cnt = s_cnt[q];
             // accumulate mode (no cap): add this tile's sums into the resident
             // per-node accumulators, re-referenced from the tile's depth to
             // the accumulators' depth.  One lane owns each node; the caller
@@ -914,25 +935,51 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                 a.acc_lo[o] = c0 > 0 ? fminf(a.acc_lo[o], lo) : lo;
                 a.acc_hi[o] = c0 > 0 ? fmaxf(a.acc_hi[o], hi) : hi;
             }
-        } else {
+        }
+    } else {
+        // outputs: the tile's first node as a scalar base, 32-bit byte
+        // offsets per lane (rows of the tile lie within 2^30 nodes of it).
+        // The nearest depth gathered in one pass is stored in the next, so
+        // the gather overlaps a pass of work.
+        constexpr int kPass = kTW * kTH / 64;
+        const size_t tbase = (size_t)ta0 * a.nx + tb0;
+        unsigned overm = 0u;  // bit p: this lane's node of pass p is over the cap
+        float bz_prev = NAN;
+        uint32_t ob_prev = 0;
+        bool st_prev = false;
+#pragma unroll 1
+        for (int p = 0; p < kPass; ++p) {
+            const int qq = p * 64 + lane;
+            const int la = qq / kTW, lb = qq - la * kTW;
+            const int q = la * kRS + lb;
+            const bool act = p * 64 < kTW * TH && la < th && lb < tw;
+            const int cnt = s_cnt[q];
+            int bi;
+            bool hit;
+            if constexpr (kKey) {
+                const unsigned long long key = s_key[q];
+                bi = (int)(key & imask);
+                hit = (key >> kb) == 0ull;
+            } else if constexpr (kPacked) {
+                bi = 0;
+                hit = false;
+            } else {
+                bi = s_bidx[q];
+                hit = s_bd2[q] == 0.0;
+            }
             const bool over = act && kcap > 0 && cnt > kcap;
+            overm |= over ? 1u << p : 0u;
+            const uint32_t ob = (uint32_t)(la * a.nx + lb) << 2;
+            float bz = NAN;
             if (act && !over) {
-                // outputs: the tile's first node as a scalar base, 32-bit
-                // byte offsets per lane (rows of the tile lie within 2^30
-                // nodes of it)
-                const size_t tbase = (size_t)ta0 * a.nx + tb0;
-                const uint32_t ob = (uint32_t)(la * a.nx + lb) << 2;
                 if (kMode & 2) {
                     if (a.nn_idx_out)
                         *byte_at(a.nn_idx_out + tbase, ob) = cnt > 0 ? bi : -1;
-                    if (a.nn_z_out) {
-                        float bz;
+                    if (a.nn_z_out && cnt > 0) {
                         if constexpr (kPacked)
-                            bz = cnt > 0 ? __int_as_float(byte_at(bv.rec, (uint32_t)bi << 4)->w)
-                                         : NAN;
+                            bz = __int_as_float(byte_at(bv.rec, (uint32_t)bi << 4)->w);
                         else
-                            bz = cnt > 0 ? s_bz[q] : NAN;
-                        *byte_at(a.nn_z_out + tbase, ob) = bz;
+                            bz = s_bz[q];
                     }
                 }
                 if constexpr (kIdw) {
@@ -953,11 +1000,26 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                         hole ? NAN : fminf(fmaxf(v, s_lo[q]), s_hi[q]);
                 }
             }
-            unsigned long long om = __ballot(over);
+            if (kMode & 2) {
+                if (a.nn_z_out && st_prev)
+                    *byte_at(a.nn_z_out + tbase, ob_prev) = bz_prev;
+            }
+            bz_prev = bz;
+            ob_prev = ob;
+            st_prev = act && !over;
+        }
+        if (kMode & 2) {
+            if (a.nn_z_out && st_prev)
+                *byte_at(a.nn_z_out + tbase, ob_prev) = bz_prev;
+        }
+        // nodes above the cap: re-done exactly by the whole wave
+#pragma unroll 1
+        for (int p = 0; p < kPass; ++p) {
+            unsigned long long om = __ballot((overm >> p) & 1u);
             while (om) {
                 const int l = __ffsll((long long)om) - 1;
                 om &= om - 1;
-                const int qn = q0 + l;
+                const int qn = p * 64 + l;
                 exact_node<kMode, kPmode, kPrec>(bv, a, g.X0, g.Y0, g.DXl, g.DYl, ta0 + qn / kTW,
                                                  tb0 + qn % kTW, zref);
             }
