@@ -626,6 +626,9 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
     // estimates only (the window origin is corrected exactly in integers)
     const float invDX = __builtin_amdgcn_rcpf((float)g.DXl),
                 invDY = __builtin_amdgcn_rcpf((float)g.DYl);
+    // squared staging reach, widened by 2^-20 against the FP32 rounding of
+    // the squared distances it is compared with
+    const float reach2 = (float)R * (float)R * (1.0f + 0x1p-20f);
 
     float zref = 0.0f;
     bool have_ref = false;
@@ -709,6 +712,14 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                 ia += (ia - 1) * g.DYl >= yr - R ? -1 : 0;
                 ia += ia * g.DYl < yr - R ? 1 : 0;
                 keep = jb <= tw - 1 && jb + g.Wx - 1 >= 0 && ia <= th - 1 && ia + g.Wy - 1 >= 0;
+                // and the disk must meet the box of the tile's in-grid nodes
+                // (a window can meet the tile with corner cells only): FP32
+                // distance to the box against the staging reach with a margin
+                // above the rounding, so no sounding that can reach a node is
+                // dropped (about one visit in ten goes)
+                const float ex = (float)max(max(-xr, xr - (tw - 1) * g.DXl), 0);
+                const float ey = (float)max(max(-yr, yr - (th - 1) * g.DYl), 0);
+                keep = keep && fmaf(ex, ex, ey * ey) <= reach2;
                 const uint32_t res = bv.res[k];
                 px = xr - jb * g.DXl;
                 py = yr - ia * g.DYl;
