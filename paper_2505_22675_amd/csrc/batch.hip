@@ -130,12 +130,17 @@ __global__ __launch_bounds__(64) void k_idw_batch_window(const IdwItem *__restri
         int seen = 0;
         for (int g = grab_size(seen, len, gmax, qwaves), t0 = pull(qhead, q, len, g); t0 >= 0;
              seen = t0 + g, g = grab_size(seen, len, gmax, qwaves), t0 = pull(qhead, q, len, g)) {
-            for (int t = t0; t < min(t0 + g, len); ++t) {
+            // the grab's work entries, one per lane, read at once
+            const int tn = min(t0 + g, len) - t0;
+            const int lane = threadIdx.x & 63;
+            int2 wl = make_int2(0, 0);
+            if (lane < tn)
+                wl = work[qoff[q] + t0 + lane];
+            for (int t = 0; t < tn; ++t) {
                 // wave-uniform work entry: the item descriptor is then read
                 // with scalar loads into SGPRs instead of vector registers
-                const int2 wv = work[qoff[q] + t];
-                const int2 w = make_int2(__builtin_amdgcn_readfirstlane(wv.x),
-                                         __builtin_amdgcn_readfirstlane(wv.y));
+                const int2 w = make_int2(__builtin_amdgcn_readlane(wl.x, t),
+                                         __builtin_amdgcn_readlane(wl.y, t));
                 const IdwItem &it = items[w.x];
                 // integer powers share one variant (the power is a runtime
                 // value there); a general power needs the window form's
@@ -173,11 +178,16 @@ __global__ __launch_bounds__(64) void k_idw_batch_dense(const IdwItem *__restric
         int seen = 0;
         for (int g = grab_size(seen, len, gmax, qwaves), t0 = pull(qhead, q, len, g); t0 >= 0;
              seen = t0 + g, g = grab_size(seen, len, gmax, qwaves), t0 = pull(qhead, q, len, g)) {
-            for (int t = t0; t < min(t0 + g, len); ++t) {
+            // the grab's work entries, one per lane, read at once
+            const int tn = min(t0 + g, len) - t0;
+            const int lane = threadIdx.x & 63;
+            int2 wl = make_int2(0, 0);
+            if (lane < tn)
+                wl = work[qoff[q] + t0 + lane];
+            for (int t = 0; t < tn; ++t) {
                 // wave-uniform work entry (scalar loads of the descriptor)
-                const int2 wv = work[qoff[q] + t];
-                const int2 w = make_int2(__builtin_amdgcn_readfirstlane(wv.x),
-                                         __builtin_amdgcn_readfirstlane(wv.y));
+                const int2 w = make_int2(__builtin_amdgcn_readlane(wl.x, t),
+                                         __builtin_amdgcn_readlane(wl.y, t));
                 const IdwItem &it = items[w.x];
                 dense::dense_tile<3, kBatchDenseK>(it.bv, it.a, w.y, it.ntx, it.pmode);
             }

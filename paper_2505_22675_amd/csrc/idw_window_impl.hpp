@@ -597,7 +597,7 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
     // accumulators cleared once the tile is known to have candidates
     auto clear_acc = [&]() {
         __syncthreads();  // the previous tile of this wave is finished with LDS
-        for (int q = lane; q < kAcc; q += 64) {
+        for (int q = lane; q < TH * kRS; q += 64) {
             s_nd[q] = make_float2(0.0f, 0.0f);
             s_cnt[q] = 0;
             s_lo[q] = INFINITY;
