@@ -408,7 +408,7 @@ def precision_report(ag, dev):
     return out
 
 
-def batched_report(ag, dev, reps=20, with_plain=True):
+def batched_report(ag, dev, reps=20, with_plain=True, tune_in=None, tune_out=None):
     """256 uneven tiles (1e3..2e5 soundings, 64^2..1024^2 nodes, p in {1,2,3}):
     the plain form (tile after tile, default bin size and kernel choice, no
     graph) against the batched form (autotuned per tile class, batched
@@ -438,12 +438,20 @@ def batched_report(ag, dev, reps=20, with_plain=True):
         n_nodes += s.grid.nx * s.grid.ny
     plain = ag.Batch(items)
     with tempfile.TemporaryDirectory() as td:
-        path = os.path.join(td, "tune.txt")
-        t0 = time.perf_counter()
-        ag.auv_batch_autotune(items, plain.ws, path)
-        tune_s = time.perf_counter() - t0
+        if tune_in:
+            # a table from an earlier run (counter passes: timing candidates
+            # under a profiler would pick from distorted times)
+            path, tune_s = tune_in, None
+        else:
+            path = os.path.join(td, "tune.txt")
+            t0 = time.perf_counter()
+            ag.auv_batch_autotune(items, plain.ws, path)
+            tune_s = time.perf_counter() - t0
         tuned = ag.Batch(items, tune_path=path)
         table = [ln.strip() for ln in open(path) if ln.startswith("class ")]
+        if tune_out:
+            with open(tune_out, "w") as f:
+                f.write("\n".join(table) + "\n")
     plans = [tuned.item_plan(i) for i in range(len(items))]
 
     def timed(fn):
@@ -492,7 +500,7 @@ def batched_report(ag, dev, reps=20, with_plain=True):
         "batched_alu_frac": round(sum(pairs.values()) * ALU_OPS_PER_PAIR / (batch_med * 1e-3)
                                   / LANE_OPS_PEAK, 4),
         "algorithmic_bytes": int(alg_bytes),
-        "autotune_s": round(tune_s, 2), "tune_table": table,
+        "autotune_s": round(tune_s, 2) if tune_s is not None else None, "tune_table": table,
         "dense_tiles": int(sum(a == ag.AUV_ALGO_DENSE for _, a in plans)),
     }
     plain.close()
@@ -600,6 +608,10 @@ def main():
                     help="skip the UTM-scale precision-variant error report")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 256-tile plain-vs-batched comparison")
+    ap.add_argument("--batch-tune", default=None,
+                    help="take the batched form's tune table from this file instead of autotuning")
+    ap.add_argument("--save-batch-tune", default=None,
+                    help="write the batched form's tune table to this file")
     ap.add_argument("--no-plain-batch", action="store_true",
                     help="batched report without the plain item-by-item comparison")
     ap.add_argument("--no-serving", action="store_true",
@@ -821,7 +833,8 @@ def main():
 
     batched = None
     if not args.no_batched:
-        batched = batched_report(ag, dev, with_plain=not args.no_plain_batch)
+        batched = batched_report(ag, dev, with_plain=not args.no_plain_batch,
+                                 tune_in=args.batch_tune, tune_out=args.save_batch_tune)
 
     serving = None
     if not args.no_serving:
