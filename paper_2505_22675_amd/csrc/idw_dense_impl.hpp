@@ -120,24 +120,27 @@ __device__ void dense_node(const auv_bin_view &bv, const IdwArgs &a, int b, int 
         list[j] = __builtin_huge_val();
     int found = 0;
 
-    auto consider = [&](int k, int Xk, int Yk) {
+    // One candidate (valid: it exists).  The insert is branch-free: a key not
+    // below the list's last entry leaves the sorted list unchanged under the
+    // min/max network, so candidates outside the disk enter as +infinity.
+    // (A branch around the network costs more: some lane of the wave nearly
+    // always inserts, and the two paths' list registers then need copies.)
+    auto consider = [&](int Ik, int Xk, int Yk, bool valid) {
         const int dX = Xk - Xn, dY = Yk - Yn;
         const long long D2 = (long long)dX * dX + (long long)dY * dY;
-        if (D2 > R2)
-            return;
-        ++found;
-        const unsigned long long key = ((unsigned long long)D2 << kb) | (unsigned)gI[k];
-        const double kd = __longlong_as_double((long long)(key + (1ull << 52)));
-        // insert into the ascending list, dropping its largest entry
-        if (kd < list[KMAX - 1]) {
+        const bool in = valid & (D2 <= R2);
+        found += in ? 1 : 0;
+        const unsigned long long key = ((unsigned long long)D2 << kb) | (unsigned)Ik;
+        const double kd =
+            in ? __longlong_as_double((long long)(key + (1ull << 52))) : __builtin_huge_val();
 #pragma unroll
-            for (int j = KMAX - 1; j > 0; --j)
-                list[j] = dmax(list[j - 1], dmin(kd, list[j]));
-            list[0] = dmin(kd, list[0]);
-        }
+        for (int j = KMAX - 1; j > 0; --j)
+            list[j] = dmax(list[j - 1], dmin(kd, list[j]));
+        list[0] = dmin(kd, list[0]);
     };
-    // the soundings of one bin segment, four at a time (their coordinates
-    // are loaded together, so the loads overlap)
+    // the soundings of one bin segment, four at a time (their coordinates and
+    // indices are loaded together, so the loads overlap; a missing fourth
+    // reloads the segment's last sounding and enters as invalid)
     auto segment = [&](int row, int c0, int c1) {
         c0 = max(c0, 0);
         c1 = min(c1, bv.nbx - 1);
@@ -146,16 +149,17 @@ __device__ void dense_node(const auv_bin_view &bv, const IdwArgs &a, int b, int 
         const int id = row * bv.nbx;
         const int e = gC[id + c1 + 1];
         for (int k = gC[id + c0]; k < e; k += 4) {
-            int Xk[4], Yk[4];
+            int Xk[4], Yk[4], Ik[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                Xk[u] = k + u < e ? gX[k + u] : 0;
-                Yk[u] = k + u < e ? gY[k + u] : 0;
+                const int kk = min(k + u, e - 1);
+                Xk[u] = gX[kk];
+                Yk[u] = gY[kk];
+                Ik[u] = gI[kk];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                if (k + u < e)
-                    consider(k + u, Xk[u], Yk[u]);
+                consider(Ik[u], Xk[u], Yk[u], k + u < e);
         }
     };
 
