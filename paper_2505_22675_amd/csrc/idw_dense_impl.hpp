@@ -44,6 +44,56 @@ __device__ inline double dmax(double a, double b)
     return r;
 }
 
+// Element k of a binned array through a 32-bit byte offset from its base
+// (k < 2^30: the dense form needs at most 30 index bits), so that a uniform
+// base takes the scalar-base form of the load instead of 64-bit addresses.
+template <class T>
+__device__ inline T ld_at(gptr<const T> base, uint32_t k)
+{
+    return *(gptr<const T>)((gptr<const char>)base + (k * (uint32_t)sizeof(T)));
+}
+
+// Compare-exchange: a takes the smaller, b the larger.
+__device__ inline void cex(double &a, double &b)
+{
+    const double lo = dmin(a, b), hi = dmax(a, b);
+    a = lo;
+    b = hi;
+}
+
+// Merge four new entries into the ascending list of the K smallest (K a
+// power of two, at least 8), keeping the K smallest of the union, ascending.
+// The four are sorted (five compare-exchanges); the element-wise minimum of
+// the list with them reversed and padded with +infinity at the front holds
+// the K smallest and is bitonic (the lower half of a bitonic half-cleaner),
+// and a bitonic merge sorts it.  In its first stage only the pairs that
+// meet a changed entry can be out of order.  Four inserts one by one would
+// take 4 (2K - 1) operations; this takes 4 + 10 + 2 (K/2 log2 K - K/2 + 4).
+template <int K>
+__device__ inline void merge4(double (&list)[K], double k0, double k1, double k2, double k3)
+{
+    static_assert(K >= 8 && (K & (K - 1)) == 0, "list length");
+    cex(k0, k1);
+    cex(k2, k3);
+    cex(k0, k2);
+    cex(k1, k3);
+    cex(k1, k2);
+    list[K - 4] = dmin(list[K - 4], k3);
+    list[K - 3] = dmin(list[K - 3], k2);
+    list[K - 2] = dmin(list[K - 2], k1);
+    list[K - 1] = dmin(list[K - 1], k0);
+#pragma unroll
+    for (int i = K / 2 - 4; i < K / 2; ++i)
+        cex(list[i], list[i + K / 2]);
+#pragma unroll
+    for (int d = K / 4; d >= 1; d >>= 1) {
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if ((i & d) == 0)
+                cex(list[i], list[i + d]);
+    }
+}
+
 // Key held in an FP64 list entry (see dense_node).
 __device__ inline unsigned long long key_of(double v)
 {
@@ -91,7 +141,7 @@ __device__ void dense_node(const auv_bin_view &bv, const IdwArgs &a, int b, int 
     constexpr bool kIdw = (kMode & 1) != 0;
     // explicitly global pointers (descriptors read from memory would
     // otherwise give flat loads)
-    const auto gX = gmem(bv.X), gY = gmem(bv.Y), gI = gmem(bv.idx);
+    const gptr<const int32_t> gX = gmem(bv.X), gY = gmem(bv.Y), gI = gmem(bv.idx);
     const auto gC = gmem(bv.cell_start);
     typedef int v4i __attribute__((ext_vector_type(4)));
     const auto gR = gmem(reinterpret_cast<const v4i *>(bv.rec));
@@ -111,55 +161,53 @@ __device__ void dense_node(const auv_bin_view &bv, const IdwArgs &a, int b, int 
 
     // The k smallest keys, ascending.  A key (below 2^62) is held as the
     // FP64 number whose bit pattern is key + 2^52: a normal positive double,
-    // so FP64 order is key order and the sorted insert is a min/max network
-    // (list'[j] = max(list[j-1], min(key, list[j]))), two full-rate FP64
-    // operations per entry instead of compares and 64-bit selects.
+    // so FP64 order is key order and the list is kept by min/max networks
+    // (full-rate FP64 operations instead of compares and 64-bit selects).
     double list[KMAX];
 #pragma unroll
     for (int j = 0; j < KMAX; ++j)
         list[j] = __builtin_huge_val();
-    int found = 0;
 
-    // One candidate (valid: it exists).  The insert is branch-free: a key not
-    // below the list's last entry leaves the sorted list unchanged under the
-    // min/max network, so candidates outside the disk enter as +infinity.
-    // (A branch around the network costs more: some lane of the wave nearly
-    // always inserts, and the two paths' list registers then need copies.)
-    auto consider = [&](int Ik, int Xk, int Yk, bool valid) {
+    // The list entry of one candidate (valid: it exists); candidates outside
+    // the disk enter as +infinity, which no merge keeps ahead of a key.  The
+    // merge is branch-free (a branch around it costs more: some lane of the
+    // wave nearly always inserts, and the two paths' list registers then need
+    // copies).  The list's finite entries are the min(found, KMAX) nearest
+    // members, so the number found is not kept: "at least j found" is
+    // list[j - 1] < inf.
+    auto entry = [&](int Ik, int Xk, int Yk, bool valid) {
         const int dX = Xk - Xn, dY = Yk - Yn;
         const long long D2 = (long long)dX * dX + (long long)dY * dY;
         const bool in = valid & (D2 <= R2);
-        found += in ? 1 : 0;
         const unsigned long long key = ((unsigned long long)D2 << kb) | (unsigned)Ik;
-        const double kd =
-            in ? __longlong_as_double((long long)(key + (1ull << 52))) : __builtin_huge_val();
-#pragma unroll
-        for (int j = KMAX - 1; j > 0; --j)
-            list[j] = dmax(list[j - 1], dmin(kd, list[j]));
-        list[0] = dmin(kd, list[0]);
+        return in ? __longlong_as_double((long long)(key + (1ull << 52))) : __builtin_huge_val();
     };
     // the soundings of one bin segment, four at a time (their coordinates and
     // indices are loaded together, so the loads overlap; a missing fourth
     // reloads the segment's last sounding and enters as invalid)
     auto segment = [&](int row, int c0, int c1) {
+        // an empty range for a segment outside the bin domain (no early
+        // return: the list stays in the same registers on every path)
         c0 = max(c0, 0);
         c1 = min(c1, bv.nbx - 1);
-        if (row < 0 || row >= bv.nby || c0 > c1)
-            return;
-        const int id = row * bv.nbx;
-        const int e = gC[id + c1 + 1];
-        for (int k = gC[id + c0]; k < e; k += 4) {
+        const bool ok = row >= 0 && row < bv.nby && c0 <= c1;
+        const int id = ok ? row * bv.nbx : 0;
+        int k = ok ? gC[id + c0] : 0;
+        const int e = ok ? gC[id + c1 + 1] : 0;
+        for (; k < e; k += 4) {
             int Xk[4], Yk[4], Ik[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int kk = min(k + u, e - 1);
-                Xk[u] = gX[kk];
-                Yk[u] = gY[kk];
-                Ik[u] = gI[kk];
+                const uint32_t kk = (uint32_t)min(k + u, e - 1);
+                Xk[u] = ld_at(gX, kk);
+                Yk[u] = ld_at(gY, kk);
+                Ik[u] = ld_at(gI, kk);
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                consider(Ik[u], Xk[u], Yk[u], k + u < e);
+            // the first candidate is always valid; without this the compiler
+            // moves its index load into a branch that waits for it alone
+            asm volatile("" : "+v"(Ik[0]));
+            merge4(list, entry(Ik[0], Xk[0], Yk[0], true), entry(Ik[1], Xk[1], Yk[1], k + 1 < e),
+                   entry(Ik[2], Xk[2], Yk[2], k + 2 < e), entry(Ik[3], Xk[3], Yk[3], k + 3 < e));
         }
     };
 
@@ -184,12 +232,16 @@ __device__ void dense_node(const auv_bin_view &bv, const IdwArgs &a, int b, int 
             const long long lb = (long long)d * B + m0;
             if (lb * lb > R2)
                 break;
-            if (found >= kcap && (long long)(key_of(list[kcap - 1]) >> kb) < lb * lb)
+            if (list[kcap - 1] < __builtin_huge_val() &&
+                (long long)(key_of(list[kcap - 1]) >> kb) < lb * lb)
                 break;
         }
     }
 
-    const int m = min(found, kcap);
+    int m = 0;  // members taken: min(found, kcap)
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j)
+        m += (j < kcap && list[j] < __builtin_huge_val()) ? 1 : 0;
     unsigned long long keys[KMAX];
 #pragma unroll
     for (int j = 0; j < KMAX; ++j)
@@ -251,9 +303,12 @@ __device__ void dense_node(const auv_bin_view &bv, const IdwArgs &a, int b, int 
 }
 
 // Whether the dense form's keys fit: (R^2 << index bits) plus the largest
-// index stays below 2^62 (the FP64 list entries hold key + 2^52).
+// index stays below 2^62 (the FP64 list entries hold key + 2^52), and the
+// binned arrays are addressed by 32-bit byte offsets (at most 30 index bits).
 __host__ __device__ inline bool dense_key_ok(int32_t R, int32_t idx_bits)
 {
+    if (idx_bits > 30)
+        return false;
     const unsigned __int128 top = ((unsigned __int128)((unsigned long long)R * (unsigned long long)R)
                                    << idx_bits) +
                                   ((unsigned __int128)1 << idx_bits);
