@@ -40,6 +40,7 @@ namespace {
 
 constexpr int kQueues = 8;
 constexpr int kBatchDenseK = 16;  // largest max_pts the persistent dense path keeps
+constexpr size_t kOvfMax = size_t(1) << 21;  // over-cap list entries at most (32 MiB)
 
 struct IdwItem {
     auv_bin_view bv;
@@ -48,19 +49,42 @@ struct IdwItem {
     int32_t ntx, ntiles;
     int32_t dense, pmode;
     int32_t span;  // sparse items: the span form covers it (else the window form)
+    // window items: nodes above the cap go to the over-cap list (cap <= 16,
+    // dense keys fit), finished by k_overcap_dense after the persistent kernels
+    int32_t cap_list;
 };
 
+// Queue heads of both forms, then the over-cap list's entry count.
 __global__ void k_reset_queues(int32_t *qhead)
 {
-    if (threadIdx.x < 2 * kQueues)
+    if (threadIdx.x < 2 * kQueues + 1)
         qhead[threadIdx.x] = 0;
 }
 
 template <int kPmode, int kChunks>
-__device__ inline void run_window(const IdwItem &it, int tile, const win::WinSmem &sm)
+__device__ inline void run_window(const IdwItem &it, int tile, const win::WinSmem &sm,
+                                  win::CapSink sink)
 {
+    if (!it.cap_list)
+        sink.count = nullptr;
     win::window_tile<3, kPmode, true, kChunks, AUV_P_FP32_REBASE>(it.bv, it.a, it.g, tile,
-                                                                  it.ntx, sm);
+                                                                  it.ntx, sm, 0, 1, nullptr, sink);
+}
+
+// The window items' nodes above the cap, one lane per node: the dense form's
+// ring search for the cap nearest.  Every tile of a wave's window kernel
+// re-did such nodes one at a time, the whole wave per node; clustered
+// soundings put hundreds of them in one tile.
+__global__ __launch_bounds__(64) void k_overcap_dense(const IdwItem *__restrict__ items,
+                                                      const int4 *__restrict__ list,
+                                                      const int32_t *__restrict__ count, int cap)
+{
+    const int n = min(*count, cap);
+    for (int e = blockIdx.x * 64 + (int)threadIdx.x; e < n; e += gridDim.x * 64) {
+        const int4 v = list[e];
+        const IdwItem &it = items[v.x];
+        dense::dense_node<3, kBatchDenseK>(it.bv, it.a, v.z, v.y, it.pmode);
+    }
 }
 
 // Grab the next `grab` work entries of queue q: returns the first (or -1 when
@@ -98,7 +122,8 @@ __global__ __launch_bounds__(64) void k_idw_batch_window(const IdwItem *__restri
                                                          const int2 *__restrict__ work,
                                                          const int32_t *__restrict__ qoff,
                                                          const int32_t *__restrict__ qgrab,
-                                                         int32_t *__restrict__ qhead, int qwaves)
+                                                         int32_t *__restrict__ qhead, int qwaves,
+                                                         int4 *__restrict__ ovf_list, int ovf_cap)
 {
     struct WinLds {
         float2 nd[win::kAcc];
@@ -153,13 +178,21 @@ __global__ __launch_bounds__(64) void k_idw_batch_window(const IdwItem *__restri
                         continue;
                     }
                 }
+                // nodes above the cap go to the over-cap list (when there is one)
+                win::CapSink sk;
+                if (ovf_list) {
+                    sk.count = qhead + 2 * kQueues;
+                    sk.list = ovf_list;
+                    sk.cap = ovf_cap;
+                    sk.item = w.x;
+                }
                 if constexpr (kGeneral) {
                     if (it.pmode == 0) {
-                        run_window<0, 1>(it, w.y, sm);
+                        run_window<0, 1>(it, w.y, sm, sk);
                         continue;
                     }
                 }
-                run_window<-1, 1>(it, w.y, sm);
+                run_window<-1, 1>(it, w.y, sm, sk);
             }
         }
     }
@@ -322,6 +355,7 @@ struct auv_batch {
     int32_t nwork_window = 0, nwork_dense = 0;
     int32_t blocks_window = 0, blocks_dense = 0;  // persistent grid sizes
     bool any_span = false, any_general = false;    // window items needing those variants
+    int32_t ovf_cap = 0;                           // entries of the over-cap list
     int32_t max_nbx = 0, max_nby = 0;  // largest bin domain of the row-binned items
     hipStream_t cap_stream2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -468,6 +502,11 @@ bool make_idw_item(const auv_batch_item &it, const auv_bin_view &bv, const IdwAr
                                       << bv.idx_bits;
         ok = ok && top < ((unsigned __int128)1 << 64);
         d.span = ok && a.span && span::span_ok(bv, a, d.g, d.pmode) ? 1 : 0;
+        d.cap_list = ok && !d.span && it.params.max_pts >= 1 &&
+                             it.params.max_pts <= kBatchDenseK &&
+                             dense::dense_key_ok(a.R, bv.idx_bits)
+                         ? 1
+                         : 0;
         const int th = win::tile_rows(a);
         d.ntx = (it.grid.nx + win::kTW - 1) / win::kTW;
         d.ntiles = d.ntx * ((it.grid.ny + th - 1) / th);
@@ -485,7 +524,7 @@ auv_status build_tables(auv_batch *b, char *ws)
     b->idw.assign(count, IdwItem{});
     b->row_items.clear();
     std::vector<int32_t> hist(1, 0), scat(1, 0), sort(1, 0);
-    std::vector<double> cost(count, 0.0);
+    std::vector<double> cost(count, 0.0), tile_cost(count, 0.0);
     for (int i = 0; i < count; ++i) {
         const auv_batch_item &it = b->items[i];
         BinWorkspace w;
@@ -505,7 +544,21 @@ auv_status build_tables(auv_batch *b, char *ws)
         IdwItem &d = b->idw[i];
         const bool ok = make_idw_item(it, bv, a, b->algo[i], &d) && row_path_ok(b->geom[i]);
         b->persistent[i] = ok ? 1 : 0;
-        cost[i] = (double)it.n + (double)it.grid.nx * it.grid.ny * (d.dense ? 4.0 : 1.0);
+        if (d.dense) {
+            cost[i] = (double)it.n + (double)it.grid.nx * it.grid.ny * 4.0;
+            tile_cost[i] = cost[i] / std::max(1, d.ntiles);
+        } else {
+            // a window tile costs a fixed part plus one visit per sounding
+            // within reach of its box (uniform density over the grid grown
+            // by the radius)
+            const double r = it.params.radius;
+            const double rho = (double)it.n / ((it.grid.nx * it.grid.dx + 2.0 * r) *
+                                               (it.grid.ny * it.grid.dy + 2.0 * r));
+            const double bw = win::kTW * it.grid.dx + 2.0 * r;
+            const double bh = win::tile_rows(a) * it.grid.dy + 2.0 * r;
+            tile_cost[i] = 20.0 + rho * bw * bh;
+            cost[i] = tile_cost[i] * std::max(1, d.ntiles);
+        }
     }
     b->nrow_items = (int32_t)b->row_items.size();
     b->hist_blocks = hist.back();
@@ -516,7 +569,12 @@ auv_status build_tables(auv_batch *b, char *ws)
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i)
         order[i] = i;
-    std::sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    // items with the longest tiles first (a wave takes a tile alone, so a
+    // long tile late in a queue would end the kernel late); to the least
+    // loaded queue by total cost
+    std::sort(order.begin(), order.end(), [&](int x, int y) {
+        return tile_cost[x] != tile_cost[y] ? tile_cost[x] > tile_cost[y] : cost[x] > cost[y];
+    });
     b->work.clear();
     std::vector<int32_t> qoff(2 * kQueues + 1, 0);
     for (int form = 0; form < 2; ++form) {
@@ -578,6 +636,7 @@ struct Tables {
     IdwItem *idw;
     int32_t *offs;
     int32_t *qhead;
+    int4 *ovf;  // over-cap list
     int2 *work;
 };
 
@@ -593,33 +652,39 @@ Tables table_ptrs(const auv_batch *b, char *ws)
     t.offs = reinterpret_cast<int32_t *>(ws + off);
     off += align256(sizeof(int32_t) * (3 * (count + 1) + 4 * kQueues + 1));
     t.qhead = reinterpret_cast<int32_t *>(ws + off);
-    off += align256(sizeof(int32_t) * 2 * kQueues);
+    off += align256(sizeof(int32_t) * (2 * kQueues + 1));
+    t.ovf = reinterpret_cast<int4 *>(ws + off);
+    off += align256(sizeof(int4) * (size_t)b->ovf_cap);
     t.work = reinterpret_cast<int2 *>(ws + off);
     return t;
 }
 
-size_t tables_size(size_t count, size_t max_tiles)
+size_t tables_size(size_t count, size_t max_tiles, size_t ovf_cap)
 {
     return align256(sizeof(RowItem) * count) + align256(sizeof(IdwItem) * count) +
            align256(sizeof(int32_t) * (3 * (count + 1) + 4 * kQueues + 1)) +
-           align256(sizeof(int32_t) * 2 * kQueues) +
+           align256(sizeof(int32_t) * (2 * kQueues + 1)) + align256(sizeof(int4) * ovf_cap) +
            align256(sizeof(int2) * std::max<size_t>(max_tiles, 1));
 }
 
 void launch_batch_window(int blocks, bool any_span, bool any_general, const IdwItem *idw,
                          const int2 *work, const int32_t *qoff, const int32_t *qgrab,
-                         int32_t *qhead, hipStream_t st)
+                         int32_t *qhead, int4 *ovf_list, int ovf_cap, hipStream_t st)
 {
     const int qw = std::max(1, blocks / kQueues);
     const unsigned nb = (unsigned)blocks;
     if (any_span && any_general)
-        k_idw_batch_window<true, true><<<nb, 64, 0, st>>>(idw, work, qoff, qgrab, qhead, qw);
+        k_idw_batch_window<true, true><<<nb, 64, 0, st>>>(idw, work, qoff, qgrab, qhead, qw,
+                                                           ovf_list, ovf_cap);
     else if (any_span)
-        k_idw_batch_window<true, false><<<nb, 64, 0, st>>>(idw, work, qoff, qgrab, qhead, qw);
+        k_idw_batch_window<true, false><<<nb, 64, 0, st>>>(idw, work, qoff, qgrab, qhead, qw,
+                                                            ovf_list, ovf_cap);
     else if (any_general)
-        k_idw_batch_window<false, true><<<nb, 64, 0, st>>>(idw, work, qoff, qgrab, qhead, qw);
+        k_idw_batch_window<false, true><<<nb, 64, 0, st>>>(idw, work, qoff, qgrab, qhead, qw,
+                                                            ovf_list, ovf_cap);
     else
-        k_idw_batch_window<false, false><<<nb, 64, 0, st>>>(idw, work, qoff, qgrab, qhead, qw);
+        k_idw_batch_window<false, false><<<nb, 64, 0, st>>>(idw, work, qoff, qgrab, qhead, qw,
+                                                             ovf_list, ovf_cap);
 }
 
 // Enqueue the whole batched form on `st` (captured by the caller).
@@ -657,10 +722,19 @@ auv_status enqueue_batched(auv_batch *b, char *ws, hipStream_t st)
         }
         if (b->nwork_window > 0)
             launch_batch_window(b->blocks_window, b->any_span, b->any_general, t.idw, t.work,
-                                qoff, qgrab, t.qhead, st);
+                                qoff, qgrab, t.qhead, b->ovf_cap > 0 ? t.ovf : nullptr,
+                                b->ovf_cap, st);
         AUV_HIP(hipGetLastError());
         if (b->nwork_dense > 0)
             AUV_HIP(hipStreamWaitEvent(st, b->ev_join, 0));
+        if (b->nwork_window > 0 && b->ovf_cap > 0) {
+            int dev = 0, cus = 256;
+            (void)hipGetDevice(&dev);
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            k_overcap_dense<<<cus * 4, 64, 0, st>>>(t.idw, t.ovf, t.qhead + 2 * kQueues,
+                                                    b->ovf_cap);
+            AUV_HIP(hipGetLastError());
+        }
     }
     for (int i = 0; i < count; ++i) {
         if (b->persistent[i])
@@ -698,7 +772,7 @@ auv_status auv_batch_plan(const auv_batch_item *items, int32_t count, const char
     b->slice_size.resize(count);
     b->persistent.assign(count, 0);
     const std::map<ClassKey, Choice> tune = read_tune(tune_path);
-    size_t off = 0, max_tiles = 0;
+    size_t off = 0, max_tiles = 0, ovf_nodes = 0;
     for (int i = 0; i < count; ++i) {
         const auv_batch_item &it = b->items[i];
         auv_status st = validate_item(it, i);
@@ -741,8 +815,14 @@ auv_status auv_batch_plan(const auv_batch_item *items, int32_t count, const char
         b->slice_size[i] = align256(need);
         const size_t tiles8 = (size_t)((it.grid.nx + 7) / 8) * ((it.grid.ny + 7) / 8);
         max_tiles += tiles8;
+        // over-cap list: room for every node of the capped window items, up
+        // to a bound (nodes beyond it are re-done inside their tiles)
+        if (b->algo[i] != AUV_ALGO_DENSE && it.params.max_pts >= 1 &&
+            it.params.max_pts <= kBatchDenseK)
+            ovf_nodes += (size_t)it.grid.nx * (size_t)it.grid.ny;
     }
-    b->tables_bytes = align256(tables_size(count, max_tiles));
+    b->ovf_cap = (int32_t)std::min<size_t>(ovf_nodes, kOvfMax);
+    b->tables_bytes = align256(tables_size(count, max_tiles, (size_t)b->ovf_cap));
     off = b->tables_bytes;
     for (int i = 0; i < count; ++i) {
         b->slice_off[i] = off;
@@ -974,7 +1054,8 @@ auv_status auv_batch_autotune(const auv_batch_item *items, int32_t count, void *
                                                                  per_queue);
                     else
                         launch_batch_window(blocks, d.span != 0, d.pmode == 0, t.idw, t.work,
-                                            t.offs, t.offs + kQueues + 1, t.qhead, st);
+                                            t.offs, t.offs + kQueues + 1, t.qhead, nullptr, 0,
+                                            st);
                     AUV_HIP(hipGetLastError());
                     return AUV_OK;
                 },

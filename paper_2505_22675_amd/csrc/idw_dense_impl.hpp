@@ -136,7 +136,8 @@ __device__ inline float wfast(float d2, int pmode, float power, float inv_r2)
 // keys (max_pts <= KMAX), then the weighted sum in key order.  Writes the
 // node's outputs.
 template <int kMode, int KMAX>
-__device__ void dense_node(const auv_bin_view &bv, const IdwArgs &a, int b, int an, int pmode)
+__device__ __forceinline__ void dense_node(const auv_bin_view &bv, const IdwArgs &a, int b, int an,
+                                           int pmode)
 {
     constexpr bool kIdw = (kMode & 1) != 0;
     // explicitly global pointers (descriptors read from memory would

@@ -522,6 +522,16 @@ struct WinSmem {
     float4 *rv;                 //   variant coordinates, depth   [64] (variants, unpacked)
 };
 
+// Where a caller collects a tile's nodes above the cap for a later pass of
+// its own (one lane per node) instead of the tile re-doing them one at a
+// time: entries (item, row, column, 0) appended at list[*count] while below cap.
+struct CapSink {
+    int32_t *count = nullptr;  // null: no sink
+    int4 *list = nullptr;
+    int32_t cap = 0;
+    int32_t item = 0;
+};
+
 // part / nparts: the wave takes every nparts-th 64-wide chunk of the tile's
 // candidates, starting at chunk `part` (several waves can share one tile).
 // In accumulate mode with nparts > 1 the wave leaves its partial sums in LDS
@@ -529,7 +539,8 @@ struct WinSmem {
 template <int kMode, int kPmode, bool kPacked, int kChunks, int kPrec>
 __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinGeom &g,
                             int tile, int ntx, const WinSmem &sm, int part = 0,
-                            int nparts = 1, float *zref_out = nullptr)
+                            int nparts = 1, float *zref_out = nullptr,
+                            CapSink sink = CapSink{})
 {
     constexpr bool kIdw = (kMode & 1) != 0;
     // the nearest key serves the nearest outputs, hits and the cap; the
@@ -1023,7 +1034,27 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
             if (a.nn_z_out && st_prev)
                 *byte_at(a.nn_z_out + tbase, ob_prev) = bz_prev;
         }
-        // nodes above the cap: re-done exactly by the whole wave
+        // nodes above the cap: handed to the caller's sink while it has room
+        if (sink.count) {
+#pragma unroll 1
+            for (int p = 0; p < kPass; ++p) {
+                const bool mine = (overm >> p) & 1u;
+                const unsigned long long m = __ballot(mine);
+                if (m == 0ull)
+                    continue;
+                int base = 0;
+                if (lane == 0)
+                    base = atomicAdd(sink.count, __popcll(m));
+                base = __shfl(base, 0, 64);
+                const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
+                if (mine && slot < sink.cap) {
+                    const int qn = p * 64 + lane;
+                    sink.list[slot] = make_int4(sink.item, ta0 + qn / kTW, tb0 + qn % kTW, 0);
+                    overm &= ~(1u << p);
+                }
+            }
+        }
+        // the others: re-done exactly by the whole wave
 #pragma unroll 1
         for (int p = 0; p < kPass; ++p) {
             unsigned long long om = __ballot((overm >> p) & 1u);

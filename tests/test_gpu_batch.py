@@ -152,6 +152,47 @@ def test_batch_mixed_parity_and_replay(ag, orc):
     b.close()
 
 
+def test_batch_overcap_nodes(ag, orc):
+    """Window-form items whose clustered soundings put most nodes above the
+    cap: those nodes are finished after the persistent kernels, one lane per
+    node (caps up to 16), or inside their tile (cap above 16).  Every node
+    against the oracle, on the first launch and on replays."""
+    rng = np.random.default_rng(97)
+    g = GridSpec(500.0, 800.0, 2.0, 2.0, 120, 88)
+    centres = rng.uniform([0, 0], [240, 176], size=(12, 2))
+    pts = np.concatenate([c + rng.normal(0, 8.0, size=(3000, 2)) for c in centres])
+    pts = np.concatenate([pts, rng.uniform([-6, -6], [246, 182], size=(3000, 2))])
+    x, y = g.x0 + pts[:, 0], g.y0 + pts[:, 1]
+    snap = np.arange(len(x)) % 3 == 0                      # lattice ties on a third
+    x[snap] = g.x0 + np.round((x[snap] - g.x0) / 0.25) * 0.25
+    y[snap] = g.y0 + np.round((y[snap] - g.y0) / 0.25) * 0.25
+    z = -3000.0 + 20.0 * np.cos((x - g.x0) / 23.0) + rng.normal(0, 2.0, len(x))
+    items = []
+    for k, p in ((4, 2.0), (16, 1.0), (9, 1.5), (20, 3.0)):
+        s = Soundings(x, y, z, g, radius=6.0, power=p, min_pts=1, max_pts=k, name=f"k{k}")
+        items.append(_Item(ag, s, algo=ag.AUV_ALGO_SPARSE))
+    b = ag.Batch([it.item for it in items])
+    assert all(b.item_plan(i)[1] == ag.AUV_ALGO_SPARSE for i in range(len(items)))
+    b.launch()
+    torch.cuda.synchronize()
+    first = [it.host() for it in items]
+    for it, out in zip(items, first):
+        assert (out["cnt"] == it.max_pts).mean() > 0.3, "too few nodes at the cap"
+        _check_item(orc, it, out, f"over-cap item {it.s.name}")
+    for rep in range(2):
+        for it in items:
+            it.clear()
+        torch.cuda.synchronize()
+        b.launch()
+        torch.cuda.synchronize()
+        for k, (it, ref) in enumerate(zip(items, first)):
+            out = it.host()
+            for key in ref:
+                assert np.array_equal(out[key], ref[key], equal_nan=True), \
+                    f"replay {rep}: item {k} output {key} differs"
+    b.close()
+
+
 def test_batch_plain_form_parity(ag, orc):
     items = _mixed_items(ag)
     b = ag.Batch([it.item for it in items])
