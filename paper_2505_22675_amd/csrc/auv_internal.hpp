@@ -165,12 +165,15 @@ RowItem make_row_item(const auv_grid *g, const BinGeom &geom, const double *x,
                       const double *y, const double *z, int64_t n, const BinWorkspace &w);
 int32_t row_hist_blocks(int64_t n);
 int32_t row_scatter_blocks(int64_t n);
-// max_nbx / max_nby: the largest bin domain among the items (sizes the LDS).
+// max_nbx / max_nby: the largest bin domain among the items (sizes the LDS);
+// keys_per_row: the largest mean of input soundings per bin row among the
+// items (picks the sort's LDS key area; longer rows stay correct, on slower
+// paths).
 auv_status launch_binning_batch(const RowItem *d_items, const int32_t *d_hist_off,
                                 const int32_t *d_scatter_off, const int32_t *d_sort_off,
                                 int32_t count, int32_t hist_blocks, int32_t scatter_blocks,
                                 int32_t sort_blocks, int32_t max_nbx, int32_t max_nby,
-                                hipStream_t st);
+                                double keys_per_row, hipStream_t st);
 
 // The work of auv_bin_points into a caller-provided handle (no allocation).
 auv_status bin_into(const auv_grid *grid, const double *x, const double *y, const double *z,

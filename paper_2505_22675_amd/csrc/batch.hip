@@ -357,6 +357,7 @@ struct auv_batch {
     bool any_span = false, any_general = false;    // window items needing those variants
     int32_t ovf_cap = 0;                           // entries of the over-cap list
     int32_t max_nbx = 0, max_nby = 0;  // largest bin domain of the row-binned items
+    double keys_per_row = 0.0;          // largest mean of soundings per bin row
     hipStream_t cap_stream2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<int32_t> row_items;  // items binned by the batched row path
@@ -521,6 +522,7 @@ auv_status build_tables(auv_batch *b, char *ws)
     const int count = (int)b->items.size();
     b->rows.assign(count, RowItem{});
     b->max_nbx = b->max_nby = 0;
+    b->keys_per_row = 0.0;
     b->idw.assign(count, IdwItem{});
     b->row_items.clear();
     std::vector<int32_t> hist(1, 0), scat(1, 0), sort(1, 0);
@@ -540,6 +542,8 @@ auv_status build_tables(auv_batch *b, char *ws)
             sort.push_back(sort.back() + b->geom[i].nby);
             b->max_nbx = std::max(b->max_nbx, b->geom[i].nbx);
             b->max_nby = std::max(b->max_nby, b->geom[i].nby);
+            b->keys_per_row =
+                std::max(b->keys_per_row, (double)it.n / std::max(1, b->geom[i].nby));
         }
         IdwItem &d = b->idw[i];
         const bool ok = make_idw_item(it, bv, a, b->algo[i], &d) && row_path_ok(b->geom[i]);
@@ -695,7 +699,7 @@ auv_status enqueue_batched(auv_batch *b, char *ws, hipStream_t st)
     const int nr = b->nrow_items;
     AUV_TRY_S(launch_binning_batch(t.rows, t.offs, t.offs + (nr + 1), t.offs + 2 * (nr + 1), nr,
                                    b->hist_blocks, b->scatter_blocks, b->sort_blocks,
-                                   b->max_nbx, b->max_nby, st));
+                                   b->max_nbx, b->max_nby, b->keys_per_row, st));
     for (int i = 0; i < count; ++i) {
         if (row_path_ok(b->geom[i]))
             continue;

@@ -565,16 +565,21 @@ __device__ void block_bitonic_sort(P a, int n)
 // row, so a row holds zero, one or two pings' worth of soundings.)
 constexpr int kColsLds = 8192;
 constexpr int kSmallRank = 64;     // largest bin ranked member by member
-constexpr int kRowLds = 8192;      // keys of a row ranked in LDS (as u32 indices)
-constexpr int kRowSortLds = kRowLds / 2;  // keys of a row bitonic-sorted in LDS (u64)
 constexpr int kRowU = 8;           // keys per thread per pass: loads kept in flight
-// rows of up to kThreads * kStageU keys are ranked in registers and written
-// out through two LDS arrays of that length, carved from the u64 key area
-constexpr int kStageU = 12;
-static_assert(2 * kThreads * kStageU * sizeof(int32_t) <=
-                  kRowSortLds * sizeof(unsigned long long),
-              "row staging does not fit the key area");
-static_assert(kThreads * kStageU <= kRowLds, "staged rows must take the LDS ranking");
+// The sort's LDS key area holds kKA u64 keys: rows of up to kKA keys are
+// bitonic-sorted there, rows of up to 2 kKA keys rank there (as u32
+// indices), and rows of up to kThreads * kSU keys are ranked in registers
+// (kSU per thread) and written out through two LDS arrays of that length
+// carved from it.  Longer rows take the global-memory paths.  Three sizes:
+// a smaller area and fewer staged keys per thread let more blocks share a
+// CU (registers and LDS), for rows that are short on average.
+template <int kKA, int kSU>
+struct SortCfg {
+    static constexpr int kBitonic = kKA, kRank = 2 * kKA, kStage = kThreads * kSU;
+    static_assert(2 * kThreads * kSU * sizeof(int32_t) <= kKA * sizeof(unsigned long long),
+                  "row staging does not fit the key area");
+    static_assert(kThreads * kSU <= 2 * kKA, "staged rows must take the LDS ranking");
+};
 
 // for (k = threadIdx.x; k < n; k += kThreads) f(k, keys[r0 + k]), with kRowU
 // key loads issued before any is used
@@ -597,9 +602,11 @@ __device__ inline void for_row_keys(KP keys, int r0, int n, F f)
     }
 }
 
+template <int kKA, int kSU>
 __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
                                unsigned long long *s_k, int *lds)
 {
+    using C = SortCfg<kKA, kSU>;
     typedef int v4i __attribute__((ext_vector_type(4)));
     const auto keys = gmem(it.keys);
     const auto row_start = gmem(it.row_start);
@@ -646,7 +653,7 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
     if (row == nby - 1 && threadIdx.x == 0)
         cell_start[(int64_t)nby * nbx] = row_start[nby];
     if (__syncthreads_or(big)) {
-        if (n <= kRowSortLds) {
+        if (n <= C::kBitonic) {
             for (int k = threadIdx.x; k < n; k += kThreads)
                 s_k[k] = keys[r0 + k];
             __syncthreads();
@@ -661,7 +668,7 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
         }
         return;
     }
-    if (n <= kRowLds) {
+    if (n <= C::kRank) {
         // scatter the indices into their bins (unordered inside a bin);
         // afterwards s_h[bx] is the end of bin bx, i.e. the start of bx + 1
         uint32_t *s_i = reinterpret_cast<uint32_t *>(s_k);
@@ -670,23 +677,23 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
             s_i[p] = (uint32_t)key;
         });
         __syncthreads();
-        if (n <= kThreads * kStageU) {
+        if (n <= C::kStage) {
             // one pass: ranks and gathers in registers, then the records are
             // placed at their sorted slots in LDS (the index list is dead by
             // then) and written out contiguously, two arrays at a time
             const int k0 = threadIdx.x;
-            uint32_t ix[kStageU];
-            int pos[kStageU];
-            int4 rr[kStageU];
+            uint32_t ix[kSU];
+            int pos[kSU];
+            int4 rr[kSU];
 #pragma unroll
-            for (int j = 0; j < kStageU; ++j) {
+            for (int j = 0; j < kSU; ++j) {
                 const int k = k0 + j * kThreads;
                 const unsigned long long key = k < n ? keys[r0 + k] : 0ull;
                 ix[j] = (uint32_t)key;
                 pos[j] = k < n ? (int)(key >> 32) : -1;  // bin column until ranked
             }
 #pragma unroll
-            for (int j = 0; j < kStageU; ++j) {
+            for (int j = 0; j < kSU; ++j) {
                 if (pos[j] >= 0) {
                     const int bx = pos[j];
                     const int b0 = bx == 0 ? 0 : s_h[bx - 1], b1 = s_h[bx];
@@ -697,14 +704,14 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
                 }
             }
 #pragma unroll
-            for (int j = 0; j < kStageU; ++j)
+            for (int j = 0; j < kSU; ++j)
                 if (pos[j] >= 0)
                     rr[j] = load_rec(ix[j]);
             int32_t *s_a = reinterpret_cast<int32_t *>(s_k);
-            int32_t *s_b = s_a + kThreads * kStageU;
+            int32_t *s_b = s_a + kThreads * kSU;
             __syncthreads();  // every rank is read: the index list is free
 #pragma unroll
-            for (int j = 0; j < kStageU; ++j)
+            for (int j = 0; j < kSU; ++j)
                 if (pos[j] >= 0) {
                     s_a[pos[j]] = rr[j].x;
                     s_b[pos[j]] = rr[j].y;
@@ -716,7 +723,7 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
             }
             __syncthreads();
 #pragma unroll
-            for (int j = 0; j < kStageU; ++j)
+            for (int j = 0; j < kSU; ++j)
                 if (pos[j] >= 0) {
                     s_a[pos[j]] = rr[j].z;
                     s_b[pos[j]] = rr[j].w;
@@ -728,7 +735,7 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
             }
             __syncthreads();
 #pragma unroll
-            for (int j = 0; j < kStageU; ++j)
+            for (int j = 0; j < kSU; ++j)
                 if (pos[j] >= 0)
                     s_a[pos[j]] = (int)ix[j];
             __syncthreads();
@@ -798,10 +805,18 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
 // LDS bytes of the row-path kernels for a bin domain of nby rows, nbx columns.
 inline size_t row_hist_lds(int nby) { return sizeof(int) * (size_t)nby; }
 inline size_t row_scatter_lds(int nby) { return sizeof(int) * (size_t)nby; }
-inline size_t row_sort_lds(int nbx)
+inline size_t row_sort_lds(int ka, int nbx)
 {
-    return sizeof(unsigned long long) * kRowSortLds + sizeof(int) * (size_t)nbx;
+    return sizeof(unsigned long long) * (size_t)ka + sizeof(int) * (size_t)nbx;
 }
+
+// Key-area configuration of the sort for rows averaging `keys_per_row`
+// input soundings: 0 (1024 keys, 4 staged per thread), 1 (2048, 8), 2 (4096, 12).
+inline int sort_config(double keys_per_row)
+{
+    return keys_per_row <= 256.0 ? 0 : keys_per_row <= 1024.0 ? 1 : 2;
+}
+inline int sort_config_ka(int c) { return c == 0 ? 1024 : c == 1 ? 2048 : 4096; }
 
 // Single-item kernels.  Dynamic LDS: 8-byte aligned base.
 __global__ __launch_bounds__(kThreads) void k_row_fill(RowItem it)
@@ -825,11 +840,12 @@ __global__ __launch_bounds__(kThreads) void k_row_scatter(RowItem it)
     row_scatter_block(it, blockIdx.x, reinterpret_cast<int *>(s_dyn), lds);
 }
 
+template <int kKA, int kSU>
 __global__ __launch_bounds__(kThreads) void k_row_sort(RowItem it)
 {
     extern __shared__ unsigned long long s_dyn[];
     __shared__ int lds[kThreads / 64];
-    row_sort_block(it, blockIdx.x, reinterpret_cast<int *>(s_dyn + kRowSortLds), s_dyn, lds);
+    row_sort_block<kKA, kSU>(it, blockIdx.x, reinterpret_cast<int *>(s_dyn + kKA), s_dyn, lds);
 }
 
 // Batched kernels: block b belongs to item item_of(off, count, b); the LDS is
@@ -861,14 +877,15 @@ __global__ __launch_bounds__(kThreads) void k_row_scatter_batch(const RowItem *i
     row_scatter_block(items[i], blockIdx.x - off[i], reinterpret_cast<int *>(s_dyn), lds);
 }
 
+template <int kKA, int kSU>
 __global__ __launch_bounds__(kThreads) void k_row_sort_batch(const RowItem *items,
                                                              const int32_t *off, int count)
 {
     extern __shared__ unsigned long long s_dyn[];
     __shared__ int lds[kThreads / 64];
     const int i = item_of(off, count, blockIdx.x);
-    row_sort_block(items[i], blockIdx.x - off[i], reinterpret_cast<int *>(s_dyn + kRowSortLds),
-                   s_dyn, lds);
+    row_sort_block<kKA, kSU>(items[i], blockIdx.x - off[i],
+                             reinterpret_cast<int *>(s_dyn + kKA), s_dyn, lds);
 }
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -1016,7 +1033,15 @@ auv_status launch_binning(const auv_grid *g, const BinGeom &geom, const double *
         if (n > 0)
             k_row_hist<<<it.nblk, kThreads, row_hist_lds(geom.nby), st>>>(it);
         k_row_scatter<<<row_scatter_blocks(n), kThreads, row_scatter_lds(geom.nby), st>>>(it);
-        k_row_sort<<<(unsigned)geom.nby, kThreads, row_sort_lds(geom.nbx), st>>>(it);
+        const int sc = sort_config((double)n / std::max(1, geom.nby));
+        const size_t sl = row_sort_lds(sort_config_ka(sc), geom.nbx);
+        const unsigned sb = (unsigned)geom.nby;
+        if (sc == 0)
+            k_row_sort<1024, 4><<<sb, kThreads, sl, st>>>(it);
+        else if (sc == 1)
+            k_row_sort<2048, 8><<<sb, kThreads, sl, st>>>(it);
+        else
+            k_row_sort<4096, 12><<<sb, kThreads, sl, st>>>(it);
         AUV_HIP(hipGetLastError());
         return AUV_OK;
     }
@@ -1056,7 +1081,7 @@ auv_status launch_binning_batch(const RowItem *d_items, const int32_t *d_hist_of
                                 const int32_t *d_scatter_off, const int32_t *d_sort_off,
                                 int32_t count, int32_t hist_blocks, int32_t scatter_blocks,
                                 int32_t sort_blocks, int32_t max_nbx, int32_t max_nby,
-                                hipStream_t st)
+                                double keys_per_row, hipStream_t st)
 {
     if (count <= 0)
         return AUV_OK;
@@ -1068,8 +1093,14 @@ auv_status launch_binning_batch(const RowItem *d_items, const int32_t *d_hist_of
                                                                              d_hist_off, count);
     k_row_scatter_batch<<<scatter_blocks, kThreads, row_scatter_lds(max_nby), st>>>(
         d_items, d_scatter_off, count);
-    k_row_sort_batch<<<sort_blocks, kThreads, row_sort_lds(max_nbx), st>>>(d_items, d_sort_off,
-                                                                           count);
+    const int sc = sort_config(keys_per_row);
+    const size_t sl = row_sort_lds(sort_config_ka(sc), max_nbx);
+    if (sc == 0)
+        k_row_sort_batch<1024, 4><<<sort_blocks, kThreads, sl, st>>>(d_items, d_sort_off, count);
+    else if (sc == 1)
+        k_row_sort_batch<2048, 8><<<sort_blocks, kThreads, sl, st>>>(d_items, d_sort_off, count);
+    else
+        k_row_sort_batch<4096, 12><<<sort_blocks, kThreads, sl, st>>>(d_items, d_sort_off, count);
     AUV_HIP(hipGetLastError());
     return AUV_OK;
 }

@@ -559,7 +559,9 @@ auv_status enqueue_launch(auv_session *s, const std::vector<Pick> &picks, int ta
     k_serve_stage<<<sgrid, kStageThreads, 0, st>>>(sa);
     AUV_TRY_S(launch_binning_batch(d_rows, d_offs, d_offs + (B + 1), d_offs + 2 * (B + 1), B,
                                    hist_off[B], scat_off[B], sort_off[B], max_nbx, max_nby,
-                                   st));
+                                   // a swath request fills a few rows of the vehicle's
+                                   // grid densely: the largest key area
+                                   1e30, st));
     // as many persistent blocks as fit at once (8 waves per CU)
     const int per_cu = std::max(1, 8 / kServeParts);
     const int blocks = (int)std::min<int64_t>((int64_t)per_cu * s->cus, 16 + ntot / 256);
