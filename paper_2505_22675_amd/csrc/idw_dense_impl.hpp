@@ -233,8 +233,13 @@ __device__ __forceinline__ void dense_node(const auv_bin_view &bv, const IdwArgs
             const long long lb = (long long)d * B + m0;
             if (lb * lb > R2)
                 break;
-            if (list[kcap - 1] < __builtin_huge_val() &&
-                (long long)(key_of(list[kcap - 1]) >> kb) < lb * lb)
+            // the cap-th key (a select chain over the list: an indexed read
+            // would copy the list into consecutive registers every ring)
+            double kth = list[0];
+#pragma unroll
+            for (int j = 1; j < KMAX; ++j)
+                kth = j == kcap - 1 ? list[j] : kth;
+            if (kth < __builtin_huge_val() && (long long)(key_of(kth) >> kb) < lb * lb)
                 break;
         }
     }
