@@ -604,11 +604,13 @@ auv_status build_tables(auv_batch *b, char *ws)
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    // waves per CU: the window kernel is bound by its LDS (about 10.6 KB per
-    // wave, 15 per CU); the dense kernel gets 8 of its 12 register-bound
-    // slots, leaving room for the window kernel on the concurrent branch
-    // (12 ran the dense items alone 19 % faster but the whole batch 6 % slower)
-    b->blocks_window = std::max(1, std::min(b->nwork_window, cus * 16));
+    // waves per CU of the two concurrent persistent kernels: the window
+    // kernel could hold 15 (its LDS, about 10.6 KB per wave) and the dense
+    // kernel 24 (80 registers), but they share the CUs.  Measured on the
+    // 256-tile batch: window 12 + dense 8 per CU 2.15 ms; window 16 + dense
+    // 8 2.33 ms, 10 + 8 2.16 ms, 8 + 8 2.27 ms; 16 + 12 2.43 ms, 16 + 6
+    // 2.33 ms, 16 + 4 2.67 ms.
+    b->blocks_window = std::max(1, std::min(b->nwork_window, cus * 12));
     b->blocks_dense = std::max(1, std::min(b->nwork_dense, cus * 8));
     b->any_span = b->any_general = false;
     for (int i = 0; i < count; ++i) {
