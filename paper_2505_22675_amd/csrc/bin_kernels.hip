@@ -456,15 +456,18 @@ __device__ void row_scatter_block(const RowItem &it, int blk, int *s_rs, int *ld
 {
     const auto cnt = gmem(it.row_count);
     const int32_t nby = it.nby;
-    int carry = 0;
-    for (int c = 0; c < nby; c += kThreads) {
-        const int i = c + threadIdx.x;
-        const int v = i < nby ? cnt[i] : 0;
-        int total;
-        const int ex = block_exclusive_scan(v, lds, &total);
-        if (i < nby)
-            s_rs[i] = carry + ex;
-        carry += total;
+    // row starts: each thread sums a run of consecutive rows, one block scan
+    // of the run sums, then each thread writes its run's starts
+    const int per = (nby + kThreads - 1) / kThreads;
+    const int r0 = min(nby, (int)threadIdx.x * per), r1 = min(nby, r0 + per);
+    int sum = 0;
+    for (int r = r0; r < r1; ++r)
+        sum += cnt[r];
+    int carry;
+    int run = block_exclusive_scan(sum, lds, &carry);
+    for (int r = r0; r < r1; ++r) {
+        s_rs[r] = run;
+        run += cnt[r];
     }
     __syncthreads();
     if (blk == 0) {
@@ -637,18 +640,29 @@ __device__ void row_sort_block(const RowItem &it, int row, int *s_h,
     });
     __syncthreads();
     const auto cs = cell_start + (int64_t)row * nbx;
-    int carry = 0, big = 0;
-    for (int c = 0; c < nbx; c += kThreads) {
-        const int bx = c + threadIdx.x;
-        const int v = bx < nbx ? s_h[bx] : 0;
-        big |= v > kSmallRank ? 1 : 0;
-        int total;
-        const int ex = block_exclusive_scan(v, lds, &total);
-        if (bx < nbx) {
-            s_h[bx] = carry + ex;  // bin start within the row
-            cs[bx] = r0 + carry + ex;
+    // bin starts within the row: each thread sums a run of consecutive
+    // columns, one block scan of the run sums, then each thread writes its
+    // run's starts into s_h; cell_start is written from s_h, coalesced
+    int big = 0;
+    {
+        const int per = (nbx + kThreads - 1) / kThreads;
+        const int c0 = min(nbx, (int)threadIdx.x * per), c1 = min(nbx, c0 + per);
+        int sum = 0;
+        for (int bx = c0; bx < c1; ++bx) {
+            const int v = s_h[bx];
+            sum += v;
+            big |= v > kSmallRank ? 1 : 0;
         }
-        carry += total;
+        int total;
+        int run = block_exclusive_scan(sum, lds, &total);
+        for (int bx = c0; bx < c1; ++bx) {
+            const int v = s_h[bx];
+            s_h[bx] = run;
+            run += v;
+        }
+        __syncthreads();
+        for (int bx = threadIdx.x; bx < nbx; bx += kThreads)
+            cs[bx] = r0 + s_h[bx];
     }
     if (row == nby - 1 && threadIdx.x == 0)
         cell_start[(int64_t)nby * nbx] = row_start[nby];
