@@ -134,7 +134,7 @@ __global__ __launch_bounds__(64) void k_idw_batch_window(const IdwItem *__restri
         float emax[kGeneral ? win::kAcc : 1];
         int beg[win::kMaxRows];
         int off[win::kMaxRows + 1];
-        int4 rec[128];
+        int4 rec[win::kRecSlots];
     };
     struct NoSpan {
         char pad[16];

@@ -503,6 +503,10 @@ constexpr int kAcc = kTH * kRS;
 // and visited one by one: the window offsets come by readlane (scalar
 // registers, where their range is known to the compiler), the rest by
 // broadcast LDS reads, which keeps the vector ALU for the per-cell work.
+// int4 slots of the kept-sounding records: 64 records of two, and one more
+// record that the visit loop's unconditional read-ahead may touch.
+constexpr int kRecSlots = 2 * 64 + 2;
+
 // Shared arrays of one window tile (pointers into the caller's LDS).
 struct WinSmem {
     float2 *nd;                 // numerator, denominator        [kAcc]
@@ -830,7 +834,36 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                         mem = in && dv <= a.r2f;
                         d2f = dv * 0x1p32f;
                     }
-                    if (mem) {
+                    if constexpr (kExact && kKey && kIdw && kPmode != 0) {
+                        // The weight, key and addresses for every lane (a masked
+                        // VALU instruction costs the same issue slot), so that
+                        // the masked block below holds the LDS operations only.
+                        // Short, it is not jumped over when no lane is a member:
+                        // every path then issues the same LDS operations, and
+                        // the waits on the next record's read-ahead stay exact
+                        // instead of waiting for this visit's updates.
+                        const int q8 = qb8 + qo[t] * 8;
+                        const int q4 = qb4 + qo[t] * 4;
+                        const float w = D2 == 0 ? kHitW
+                                                : weight_nonhit(d2f, kPmode > 0 ? kPmode : a.pmode);
+                        const unsigned long long key =
+                            ((unsigned long long)D2 << kb) | (unsigned)sidx;
+                        asm volatile("" ::"v"(w), "v"(key), "v"(q8), "v"(q4));
+                        if (mem) {
+                            float2 *const pn =
+                                reinterpret_cast<float2 *>(reinterpret_cast<char *>(s_nd) + q8);
+                            float2 nd = *pn;
+                            lds_min(reinterpret_cast<unsigned long long *>(
+                                        reinterpret_cast<char *>(s_key) + q8),
+                                    key);
+                            lds_add(reinterpret_cast<int *>(reinterpret_cast<char *>(s_cnt) + q4), 1);
+                            lds_min(reinterpret_cast<float *>(reinterpret_cast<char *>(s_lo) + q4), spz);
+                            lds_max(reinterpret_cast<float *>(reinterpret_cast<char *>(s_hi) + q4), spz);
+                            nd.x = fmaf(w, sdz, nd.x);
+                            nd.y += w;
+                            *pn = nd;
+                        }
+                    } else if (mem) {
                         const int q = qb + qo[t];
                         const int q8 = qb8 + qo[t] * 8;
                         const int q4 = qb4 + qo[t] * 4;
@@ -899,25 +932,24 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
             };
             // The next record is read while the current one is applied (two
             // register sets, so the prefetch needs no copies); the records
-            // were written before the wave barrier above.
+            // were written before the wave barrier above.  The read-ahead is
+            // unconditional (past the last record it reads the spare slot and
+            // the value goes unused), so every path issues the same LDS
+            // operations and the waits on them stay exact.
             v4i a0 = rp0[0], a1 = rp0[1], b0, b1;
             while (m) {
                 int l = __ffsll((long long)m) - 1;
                 m &= m - 1ull;
-                if (m) {
-                    b0 = rp0[2];
-                    b1 = rp0[3];
-                }
+                b0 = rp0[2];
+                b1 = rp0[3];
                 visit(l, a0, a1);
                 rp0 += 2;
                 if (!m)
                     break;
                 l = __ffsll((long long)m) - 1;
                 m &= m - 1ull;
-                if (m) {
-                    a0 = rp0[2];
-                    a1 = rp0[3];
-                }
+                a0 = rp0[2];
+                a1 = rp0[3];
                 visit(l, b0, b1);
                 rp0 += 2;
             }
@@ -1085,7 +1117,7 @@ __global__ __launch_bounds__(64) void k_idw_window(auv_bin_view bv, IdwArgs a, W
     __shared__ float s_emax[kPmode == 0 ? kAcc : 1];
     __shared__ int s_beg[kMaxRows];
     __shared__ int s_off[kMaxRows + 1];
-    __shared__ int4 s_rec[128];
+    __shared__ int4 s_rec[kRecSlots];
     __shared__ float4 s_rv[kPrec == AUV_P_FP32_REBASE && kPacked ? 1 : 64];
     const WinSmem sm{s_nd, s_cnt, s_lo, s_hi, s_key, s_bd2, s_bidx, s_bz, s_emax, s_beg, s_off,
                      s_rec, s_rec + 1, s_rv};

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(64 * kServeParts) void k_serve_update(
     __shared__ float s_emax[1];
     __shared__ int s_beg[kServeParts][win::kMaxRows];
     __shared__ int s_off[kServeParts][win::kMaxRows + 1];
-    __shared__ int4 s_rec[kServeParts][128];
+    __shared__ int4 s_rec[kServeParts][win::kRecSlots];
     __shared__ float s_zref[kServeParts];
     __shared__ int s_task;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
