@@ -492,9 +492,12 @@ __device__ void exact_node(const auv_bin_view &bv, const IdwArgs &a, int X0, int
     }
 }
 
-// LDS accumulators are structure-of-arrays with a padded row stride, so that
-// the 7-row window of one sounding spreads over the banks.
-constexpr int kRS = kTW + 2;
+// LDS accumulators are structure-of-arrays, one row of the tile after the
+// other.  Unpadded: a padded stride (18) spreads a sounding's 7-row window
+// over more banks, but its 896 more bytes per wave held a CU to 15 waves
+// instead of 16 (at the 2M-sounding swath 235 us padded, 216 us unpadded;
+// a stride of 17, also 16 waves, 222 us).
+constexpr int kRS = kTW;
 constexpr int kAcc = kTH * kRS;
 
 // kChunks = window cells / 64 rounded up (compile-time, so the visit loop has
