@@ -997,24 +997,31 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
         // outputs: the tile's first node as a scalar base, 32-bit byte
         // offsets per lane (rows of the tile lie within 2^30 nodes of it).
         // The nearest depth gathered in one pass is stored in the next, so
-        // the gather overlaps a pass of work.
+        // the gather overlaps a pass of work (the passes are unrolled: in a
+        // loop, carrying the gathered value to the next iteration made the
+        // compiler wait for it at the end of its own pass).
         constexpr int kPass = kTW * kTH / 64;
         const size_t tbase = (size_t)ta0 * a.nx + tb0;
         unsigned overm = 0u;  // bit p: this lane's node of pass p is over the cap
         float bz_prev = NAN;
         uint32_t ob_prev = 0;
         bool st_prev = false;
-#pragma unroll 1
+#pragma unroll
         for (int p = 0; p < kPass; ++p) {
             const int qq = p * 64 + lane;
             const int la = qq / kTW, lb = qq - la * kTW;
             const int q = la * kRS + lb;
             const bool act = p * 64 < kTW * TH && la < th && lb < tw;
             const int cnt = s_cnt[q];
+            // the node's sums and bounds read with its count and key, one
+            // wait for all (the reads are in bounds for every lane)
+            const float2 ndv = s_nd[q];
+            const float lov = s_lo[q], hiv = s_hi[q];
             int bi;
             bool hit;
             if constexpr (kKey) {
                 const unsigned long long key = s_key[q];
+                asm volatile("" ::"v"(cnt), "v"(key), "v"(ndv.x), "v"(ndv.y), "v"(lov), "v"(hiv));
                 bi = (int)(key & imask);
                 hit = (key >> kb) == 0ull;
             } else if constexpr (kPacked) {
@@ -1045,7 +1052,7 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                     // a hit (best D^2 == 0) carries a dominant weight, so the
                     // ratio is the mean of the hits, and it beats min_pts
                     const bool hole = cnt == 0 || (cnt < a.min_pts && !hit);
-                    const float2 nd = s_nd[q];
+                    const float2 nd = ndv;
                     // the quotient num / den and the return to absolute depth
                     // in FP64 (the hardware reciprocal refined by a Newton
                     // step, then one residual correction of the quotient),
@@ -1053,8 +1060,7 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                     // (FP32 values, and rounding is monotonic, so this equals
                     // clamping before the rounding)
                     const float v = (float)((double)zref + quotient64(nd.x, nd.y));
-                    *byte_at(a.z_out + tbase, ob) =
-                        hole ? NAN : fminf(fmaxf(v, s_lo[q]), s_hi[q]);
+                    *byte_at(a.z_out + tbase, ob) = hole ? NAN : fminf(fmaxf(v, lov), hiv);
                 }
             }
             if (kMode & 2) {
