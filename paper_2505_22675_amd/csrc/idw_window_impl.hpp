@@ -840,11 +840,12 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
                     if constexpr (kExact && kKey && kIdw && kPmode != 0) {
                         // The weight, key and addresses for every lane (a masked
                         // VALU instruction costs the same issue slot), so that
-                        // the masked block below holds the LDS operations only.
-                        // Short, it is not jumped over when no lane is a member:
-                        // every path then issues the same LDS operations, and
-                        // the waits on the next record's read-ahead stay exact
-                        // instead of waiting for this visit's updates.
+                        // the masked block below holds the LDS updates only and
+                        // the record's fields are read before it: their wait no
+                        // longer sits inside the block, where it had to cover
+                        // every LDS operation issued before (the compiler keeps
+                        // the jump over a block with LDS operations, so it
+                        // counts outstanding operations for the shortest path).
                         const int q8 = qb8 + qo[t] * 8;
                         const int q4 = qb4 + qo[t] * 4;
                         const float w = D2 == 0 ? kHitW
@@ -937,8 +938,9 @@ __device__ void window_tile(const auv_bin_view &bv, const IdwArgs &a, const WinG
             // register sets, so the prefetch needs no copies); the records
             // were written before the wave barrier above.  The read-ahead is
             // unconditional (past the last record it reads the spare slot and
-            // the value goes unused), so every path issues the same LDS
-            // operations and the waits on them stay exact.
+            // the value goes unused): issued on every path, it lets the
+            // compiler wait for a record's own reads instead of for every LDS
+            // operation before them.
             v4i a0 = rp0[0], a1 = rp0[1], b0, b1;
             while (m) {
                 int l = __ffsll((long long)m) - 1;
